@@ -1,0 +1,167 @@
+"""FP64 CPU oracle for cRMSD (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports it, and this package never imports the
+product.  The arithmetic lives in ``crmsd_oracle.c`` (plain C, FP64, OpenMP):
+the definition of cRMSD (Algorithms, Eq. 1) evaluated with an explicit Kabsch
+superposition (one-sided Jacobi SVD of the 3x3 correlation matrix, proper
+rotation, explicit residual).  Every function takes float32 or float64
+coordinates and promotes them exactly to float64.
+
+Parity status: pinned (see ``tests/test_oracle_*.py``: invariants, closed
+forms, library-routine equalities, brute force on tiny inputs, finite
+differences for the gradient).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "crmsd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_crmsd.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+               "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    i64, cint = ctypes.c_int64, ctypes.c_int
+    lib.oracle_crmsd_pair.restype = ctypes.c_double
+    lib.oracle_crmsd_pair.argtypes = [dp, dp, i64]
+    lib.oracle_kabsch_rotation.restype = None
+    lib.oracle_kabsch_rotation.argtypes = [dp, dp, i64, dp]
+    lib.oracle_max_threads.restype = cint
+    lib.oracle_crmsd_matrix.argtypes = [dp, i64, i64, dp, cint]
+    lib.oracle_crmsd_pairs.argtypes = [dp, i64, i64, lp, lp, i64, dp, cint]
+    lib.oracle_crmsd_cross.argtypes = [dp, i64, dp, i64, i64, dp, cint]
+    lib.oracle_crmsd_grad_pair.argtypes = [dp, dp, i64, dp, dp, dp]
+    lib.oracle_crmsd_matrix_grad.argtypes = [dp, i64, i64, dp, dp, cint]
+    lib.oracle_crmsd_cross_grad.argtypes = [dp, i64, dp, i64, i64, dp, dp, dp, cint]
+    for f in ("oracle_crmsd_matrix", "oracle_crmsd_pairs", "oracle_crmsd_cross",
+              "oracle_crmsd_grad_pair", "oracle_crmsd_matrix_grad", "oracle_crmsd_cross_grad"):
+        getattr(lib, f).restype = cint
+    _lib = lib
+    return lib
+
+
+def _d(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _p(x):
+    return x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"{what}: oracle rejected its arguments (code {rc})")
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def crmsd(a, b) -> float:
+    """cRMSD of two [L,3] models."""
+    a, b = _d(a), _d(b)
+    assert a.shape == b.shape and a.ndim == 2 and a.shape[1] == 3
+    return float(_load().oracle_crmsd_pair(_p(a), _p(b), a.shape[0]))
+
+
+def rotation(a, b) -> np.ndarray:
+    """Optimal proper rotation R with R (a - mean a) ~ (b - mean b)."""
+    a, b = _d(a), _d(b)
+    R = np.zeros((3, 3))
+    _load().oracle_kabsch_rotation(_p(a), _p(b), a.shape[0], _p(R))
+    return R
+
+
+def crmsd_matrix(x, threads: int = 0) -> np.ndarray:
+    """Packed upper triangle [N(N-1)/2] (i<j, row-major) of an [N,L,3] ensemble."""
+    x = _d(x)
+    N, L = x.shape[0], x.shape[1]
+    out = np.zeros(N * (N - 1) // 2)
+    _check(_load().oracle_crmsd_matrix(_p(x), N, L, _p(out), threads), "crmsd_matrix")
+    return out
+
+
+def crmsd_pairs(x, I, J, threads: int = 0) -> np.ndarray:
+    """cRMSD of selected pairs (I[p], J[p]) of one ensemble."""
+    x = _d(x)
+    I = np.ascontiguousarray(I, dtype=np.int64)
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    out = np.zeros(I.shape[0])
+    lp = ctypes.POINTER(ctypes.c_int64)
+    _check(_load().oracle_crmsd_pairs(_p(x), x.shape[0], x.shape[1], I.ctypes.data_as(lp),
+                                      J.ctypes.data_as(lp), I.shape[0], _p(out), threads),
+           "crmsd_pairs")
+    return out
+
+
+def crmsd_cross(a, b, threads: int = 0) -> np.ndarray:
+    """Dense [Na, Nb] cRMSD between two sets of models of equal L."""
+    a, b = _d(a), _d(b)
+    out = np.zeros((a.shape[0], b.shape[0]))
+    _check(_load().oracle_crmsd_cross(_p(a), a.shape[0], _p(b), b.shape[0], a.shape[1],
+                                      _p(out), threads), "crmsd_cross")
+    return out
+
+
+def crmsd_grad_pair(a, b):
+    """(rmsd, dRMSD/dA, dRMSD/dB) for one pair."""
+    a, b = _d(a), _d(b)
+    gA, gB = np.zeros_like(a), np.zeros_like(b)
+    r = np.zeros(1)
+    _check(_load().oracle_crmsd_grad_pair(_p(a), _p(b), a.shape[0], _p(gA), _p(gB), _p(r)),
+           "crmsd_grad_pair")
+    return float(r[0]), gA, gB
+
+
+def crmsd_matrix_grad(x, g, threads: int = 0) -> np.ndarray:
+    """d/dX of sum_{i<j} g[k(i,j)] cRMSD_ij, shape [N,L,3]."""
+    x, g = _d(x), _d(g)
+    N = x.shape[0]
+    assert g.shape == (N * (N - 1) // 2,)
+    out = np.zeros_like(x)
+    _check(_load().oracle_crmsd_matrix_grad(_p(x), N, x.shape[1], _p(g), _p(out), threads),
+           "crmsd_matrix_grad")
+    return out
+
+
+def crmsd_cross_grad(a, b, g, threads: int = 0):
+    """(d/dA, d/dB) of sum_{ia,ib} g[ia,ib] cRMSD(A_ia, B_ib)."""
+    a, b, g = _d(a), _d(b), _d(g)
+    assert g.shape == (a.shape[0], b.shape[0])
+    gA, gB = np.zeros_like(a), np.zeros_like(b)
+    _check(_load().oracle_crmsd_cross_grad(_p(a), a.shape[0], _p(b), b.shape[0], a.shape[1],
+                                           _p(g), _p(gA), _p(gB), threads), "crmsd_cross_grad")
+    return gA, gB
+
+
+def packed_index(i, j, N):
+    """k(i,j) = i(2N-i-1)/2 + j-i-1 for i<j (int64)."""
+    i = np.asarray(i, dtype=np.int64)
+    j = np.asarray(j, dtype=np.int64)
+    return i * (2 * N - i - 1) // 2 + j - i - 1

@@ -1,0 +1,90 @@
+"""The pins must be able to fail: plant plausible mistakes in a copy of the
+oracle's C source (dropped sign term, transposed operand, dropped centring,
+wrong normalisation, wrong rotation sign, wrong singular-value order), build
+each mutant on the CPU, and check that the pin checks reject every one while
+accepting the unmodified source."""
+import ctypes
+import json
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1302_4000_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(os.path.dirname(HERE), "oracle", "crmsd_oracle.c")
+
+MUTANTS = {
+    "no_sign_term": ("double d = det3(VUt) < 0.0 ? -1.0 : 1.0;", "double d = 1.0;"),
+    "transposed_H": ("H[p][q] += a[3 * i + p] * b[3 * i + q];",
+                     "H[q][p] += a[3 * i + p] * b[3 * i + q];"),
+    "no_centring": ("for (int k = 0; k < 3; ++k) c[k] /= (double)L;",
+                    "for (int k = 0; k < 3; ++k) c[k] = 0.0;"),
+    "wrong_norm": ("return sqrt(res / (double)L);", "return sqrt(res / (double)(L + 1));"),
+    "rotation_sign": ("W[i][p] = c * wp - sn * wq;", "W[i][p] = c * wp + sn * wq;"),
+    "ascending_sort": ("if (n[ord[b]] > n[ord[a]])", "if (n[ord[b]] < n[ord[a]])"),
+}
+
+
+def build_variant(tmp_path, name, src):
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(src)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", str(so),
+                    str(c), "-lm"], check=True)
+    lib = ctypes.CDLL(str(so))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_crmsd_pair.restype = ctypes.c_double
+    lib.oracle_crmsd_pair.argtypes = [dp, dp, ctypes.c_int64]
+
+    def crmsd(a, b):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        return lib.oracle_crmsd_pair(a.ctypes.data_as(dp), b.ctypes.data_as(dp), a.shape[0])
+    return crmsd
+
+
+def pins_hold(crmsd):
+    """A compact subset of the pins; returns the names of those that fail."""
+    failed = []
+    cases = json.load(open(os.path.join(HERE, "golden", "hand_worked.json")))["cases"]
+    for c in cases:
+        if "B" not in c:
+            continue
+        A, B = np.array(c["A"], float), np.array(c["B"], float)
+        if abs(crmsd(A, B) - c["rmsd"]) > 1e-9:
+            failed.append("golden:" + c["name"])
+    rng = np.random.default_rng(0)
+    x = synth.make_ensemble(31, 6, 25).astype(np.float64)
+    R = synth.random_rotations(rng, 1)[0]
+    if crmsd(x[0], x[0] @ R.T + 7.0) > 1e-9:
+        failed.append("rigid_copy")
+    if abs(crmsd(x[1] + 5.0, x[2]) - crmsd(x[1], x[2])) > 1e-9:
+        failed.append("translation")
+    for i, j in [(0, 1), (2, 3), (4, 5)]:
+        a, b = x[i] - x[i].mean(0), x[j] - x[j].mean(0)
+        U, S, Vt = np.linalg.svd(a.T @ b)
+        d = np.sign(np.linalg.det(Vt.T @ U.T))
+        Rk = Vt.T @ np.diag([1, 1, d]) @ U.T
+        want = np.sqrt(((a @ Rk.T - b) ** 2).sum() / len(a))
+        if abs(crmsd(x[i], x[j]) - want) > 1e-9:
+            failed.append(f"svd_{i}{j}")
+    A = synth.random_walk(np.random.default_rng(5), 30)
+    if crmsd(A, A @ np.diag([1, 1, -1.0])) < 0.5:
+        failed.append("mirror")
+    return failed
+
+
+def test_unmodified_source_passes(tmp_path):
+    assert pins_hold(build_variant(tmp_path, "orig", open(SRC).read())) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site moved; update the test"
+    failed = pins_hold(build_variant(tmp_path, name, src.replace(old, new)))
+    assert failed, f"mutant {name} passed every pin"
