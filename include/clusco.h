@@ -1,0 +1,173 @@
+/*
+ * clusco.h - C ABI of the gfx950 (MI355X) cRMSD library.
+ *
+ * The operation is the coordinate RMSD after optimal superposition
+ * (Algorithms, Eq. 1) evaluated without a rotation matrix or an SVD through
+ * Eq. 2:
+ *
+ *     cRMSD(A,B) = sqrt(R_A^2 + R_B^2 - 2 (sqrt(l1) + sqrt(l2) + S sqrt(l3)))
+ *
+ * where R_A is the radius of gyration of model A, M = (1/L) sum_i a_i b_i^T is
+ * the 3x3 covariance of the centred models, l1 >= l2 >= l3 are the
+ * eigenvalues of M^T M (roots of its characteristic cubic) and S is the sign
+ * of det M (Algorithms, the paragraph after Eq. 2).  Over an ensemble of N
+ * models the library produces the N(N-1)/2 all-versus-all scores the paper
+ * counts (Background) or the scores of many models against references
+ * (Results and Discussion: comparison with a reference model).
+ *
+ * Conventions shared by every entry point
+ *  - Coordinates: device memory, float32, [models][L][3] row-major, models
+ *    back to back, 4-byte aligned.  Units are Angstrom in and out.  Every
+ *    model of one call has the same L and atom i of one model corresponds to
+ *    atom i of every other (Eq. 1).
+ *  - Packed output: device float32 [N(N-1)/2]; the score of the pair (i, j),
+ *    i < j, is at k(i,j) = i(2N-i-1)/2 + (j-i-1) (row-major upper triangle,
+ *    diagonal omitted; the same order as SciPy's condensed distance vector).
+ *  - Workspace: device memory owned by the caller, at least the size the
+ *    matching *_workspace_size call returns, 256-byte aligned.  Its contents
+ *    need no initialisation and are scratch after the call returns
+ *    (the fix-up counter excepted, see clusco_fixup_count).
+ *  - stream: a hipStream_t passed as void* (NULL = the default stream).  All
+ *    work is enqueued asynchronously; no call synchronises the host, except
+ *    clusco_fixup_count.  Kernel faults surface at the caller's next sync.
+ *  - Errors: every entry point returns a status and never aborts.  Argument
+ *    errors are detected on the host before anything is enqueued.  A failed
+ *    launch returns CLUSCO_ERR_HIP (text via clusco_last_error).
+ *  - Non-finite coordinates propagate to NaN scores; they are not detected.
+ *  - A handle is not thread-safe; use one per host thread.
+ */
+#ifndef CLUSCO_H
+#define CLUSCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CLUSCO_OK = 0,
+    CLUSCO_ERR_INVALID_ARG = 1, /* null pointer, negative size, L < 1, bad alignment */
+    CLUSCO_ERR_WORKSPACE = 2,   /* workspace null or smaller than required */
+    CLUSCO_ERR_UNSUPPORTED = 3, /* precision or size this build does not handle */
+    CLUSCO_ERR_HIP = 4          /* a HIP runtime call or launch failed */
+} clusco_status;
+
+/* Arithmetic of the covariance contraction.  The cubic solve and the final
+ * combine of Eq. 2 always run in FP64; so does the fix-up of pairs whose
+ * contraction error could exceed the mode's tolerance.
+ *   FP32        FP32 MFMA products, FP32 accumulation.    tolerance 1e-4 A
+ *   SPLIT_BF16  centred coordinates split a = hi + lo in bfloat16, three
+ *               products hi*hi' + hi*lo' + lo*hi' on MFMA, FP32 accumulation.
+ *                                                          tolerance 5e-4 A
+ *   SPLIT_FP16  the same split in float16 (|coordinate| < 65504 A).
+ *                                                          tolerance 1e-4 A
+ *   FP64        FP64 products and accumulation.           tolerance 1e-6 A */
+typedef enum {
+    CLUSCO_FP32 = 0,
+    CLUSCO_SPLIT_BF16 = 1,
+    CLUSCO_SPLIT_FP16 = 2,
+    CLUSCO_FP64 = 3
+} clusco_precision;
+
+typedef struct clusco_ctx *clusco_handle;
+
+/* Create a handle bound to HIP device `device`.  Owns host state only (device
+ * properties, tolerances, cached plans); allocates no device memory. */
+clusco_status clusco_create(clusco_handle *h, int device);
+void clusco_destroy(clusco_handle h);
+const char *clusco_status_string(clusco_status s);
+/* Text of the last failure on this handle ("" if none).  Owned by the handle. */
+const char *clusco_last_error(clusco_handle h);
+
+/* Absolute tolerance (A) that decides which pairs the FP64 fix-up recomputes
+ * for precision p.  tol <= 0 disables the fix-up (raw contraction results,
+ * for error studies).  Defaults are the tolerances listed above. */
+clusco_status clusco_set_tolerance(clusco_handle h, clusco_precision p, double tol);
+
+/* ----------------------------------------------------------- all-vs-all */
+
+/* Workspace bytes for clusco_crmsd_matrix with these sizes (0 if invalid). */
+size_t clusco_crmsd_workspace_size(clusco_handle h, int64_t N, int64_t L, clusco_precision p);
+
+/* All-vs-all cRMSD of N models of L atoms (Eq. 2 for every pair i < j).
+ * coords: device float32 [N][L][3].  out: device float32 [N(N-1)/2], packed.
+ * N in {0, 1} returns CLUSCO_OK with nothing enqueued.  L = 1 gives zeros. */
+clusco_status clusco_crmsd_matrix(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                  clusco_precision p, float *out, void *ws, size_t ws_bytes,
+                                  void *stream);
+
+/* Number of 32x32 pair blocks the last forward call on this workspace sent to
+ * the FP64 fix-up.  Synchronises `stream`.  For diagnostics only. */
+clusco_status clusco_fixup_count(clusco_handle h, const void *ws, int64_t *count, void *stream);
+
+/* ------------------------------------------------------------- batched */
+
+/* Workspace bytes for a batched call over E ensembles with host arrays
+ * h_N[E], h_L[E] (0 if invalid). */
+size_t clusco_crmsd_batched_workspace_size(clusco_handle h, int32_t E, const int64_t *h_N,
+                                           const int64_t *h_L, clusco_precision p);
+
+/* E independent ensembles in one launch sequence.  Ensemble e has h_N[e]
+ * models of h_L[e] atoms starting at float element h_coord_off[e] of coords,
+ * and its packed output (h_N[e](h_N[e]-1)/2 scores) starts at float element
+ * h_out_off[e] of out.  h_* are HOST arrays read during the call; the plan
+ * built from them is cached in the handle, so repeated calls with the same
+ * shapes enqueue without host-side planning.  Ensembles may not overlap in
+ * out. */
+clusco_status clusco_crmsd_batched(clusco_handle h, int32_t E, const int64_t *h_N,
+                                   const int64_t *h_L, const int64_t *h_coord_off,
+                                   const int64_t *h_out_off, const float *coords,
+                                   clusco_precision p, float *out, void *ws, size_t ws_bytes,
+                                   void *stream);
+
+/* ------------------------------------------------------- many-vs-reference */
+
+/* Workspace bytes for clusco_crmsd_cross. */
+size_t clusco_crmsd_cross_workspace_size(clusco_handle h, int64_t Na, int64_t Nb, int64_t L,
+                                         clusco_precision p);
+
+/* Dense cRMSD between two sets: out[ia*Nb + ib] = cRMSD(A_ia, B_ib).
+ * A: device float32 [Na][L][3], B: device float32 [Nb][L][3], out: device
+ * float32 [Na][Nb].  Nb = 1 is the comparison of every model with one
+ * reference structure (Results and Discussion, the -e mode). */
+clusco_status clusco_crmsd_cross(clusco_handle h, const float *A, int64_t Na, const float *B,
+                                 int64_t Nb, int64_t L, clusco_precision p, float *out,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------------- backward */
+
+/* Workspace bytes for clusco_crmsd_backward. */
+size_t clusco_crmsd_backward_workspace_size(clusco_handle h, int64_t N, int64_t L,
+                                            clusco_precision p);
+
+/* Gradient of sum_{i<j} grad_out[k(i,j)] * cRMSD_ij with respect to coords
+ * (derived from Eq. 1/Eq. 2: d cRMSD / d a_l = (a_l - Q b_l) / (L cRMSD) with
+ * Q = U diag(1,1,S) V^T for M = U diag(s) V^T, and the mirror formula for b).
+ * rmsd: the packed scores of a forward call on the same coords (device).
+ * grad_out: device float32 packed.  grad_coords: device float32 [N][L][3],
+ * overwritten.  Pairs whose score is 0 contribute nothing. */
+clusco_status clusco_crmsd_backward(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                    const float *rmsd, const float *grad_out,
+                                    clusco_precision p, float *grad_coords, void *ws,
+                                    size_t ws_bytes, void *stream);
+
+/* Workspace bytes for clusco_crmsd_cross_backward. */
+size_t clusco_crmsd_cross_backward_workspace_size(clusco_handle h, int64_t Na, int64_t Nb,
+                                                  int64_t L, clusco_precision p);
+
+/* Gradient of sum grad_out[ia*Nb+ib] * cRMSD(A_ia, B_ib): grad_A [Na][L][3]
+ * and grad_B [Nb][L][3] (device float32, overwritten; grad_B may be NULL).
+ * rmsd: the dense scores of a clusco_crmsd_cross call on the same inputs. */
+clusco_status clusco_crmsd_cross_backward(clusco_handle h, const float *A, int64_t Na,
+                                          const float *B, int64_t Nb, int64_t L,
+                                          const float *rmsd, const float *grad_out,
+                                          clusco_precision p, float *grad_A, float *grad_B,
+                                          void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLUSCO_H */

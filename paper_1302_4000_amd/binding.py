@@ -1,0 +1,165 @@
+"""ctypes binding of libclusco.so (include/clusco.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (outputs and workspaces come from
+its caching allocator) and the current stream.  If the library is not built
+every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclusco.so")
+
+OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = range(5)
+PRECISION = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2, "fp64": 3}
+
+_lib = None
+_lock = threading.Lock()
+_handles: dict[int, ctypes.c_void_p] = {}
+
+
+class ClucsoError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        names = {1: "INVALID_ARG", 2: "WORKSPACE", 3: "UNSUPPORTED", 4: "HIP"}
+        super().__init__(f"{what}: CLUSCO_ERR_{names.get(status, status)}"
+                         + (f" ({detail})" if detail else ""))
+
+
+def lib():
+    """Load libclusco.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; "
+                               "g.build()'` first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i64, i32, d = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        st = ctypes.c_int
+        sig = {
+            "clusco_create": (st, [ctypes.POINTER(vp), ctypes.c_int]),
+            "clusco_destroy": (None, [vp]),
+            "clusco_status_string": (ctypes.c_char_p, [st]),
+            "clusco_last_error": (ctypes.c_char_p, [vp]),
+            "clusco_set_tolerance": (st, [vp, st, d]),
+            "clusco_crmsd_workspace_size": (sz, [vp, i64, i64, st]),
+            "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
+            "clusco_fixup_count": (st, [vp, vp, i64p, vp]),
+            "clusco_crmsd_batched_workspace_size": (sz, [vp, i32, i64p, i64p, st]),
+            "clusco_crmsd_batched": (st, [vp, i32, i64p, i64p, i64p, i64p, vp, st, vp, vp, sz, vp]),
+            "clusco_crmsd_cross_workspace_size": (sz, [vp, i64, i64, i64, st]),
+            "clusco_crmsd_cross": (st, [vp, vp, i64, vp, i64, i64, st, vp, vp, sz, vp]),
+            "clusco_crmsd_backward_workspace_size": (sz, [vp, i64, i64, st]),
+            "clusco_crmsd_backward": (st, [vp, vp, i64, i64, vp, vp, st, vp, vp, sz, vp]),
+            "clusco_crmsd_cross_backward_workspace_size": (sz, [vp, i64, i64, i64, st]),
+            "clusco_crmsd_cross_backward": (st, [vp, vp, i64, vp, i64, i64, vp, vp, st, vp, vp,
+                                                 vp, sz, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+        return L
+
+
+def handle(device: int) -> ctypes.c_void_p:
+    h = _handles.get(device)
+    if h is None:
+        h = ctypes.c_void_p()
+        rc = lib().clusco_create(ctypes.byref(h), device)
+        if rc != OK:
+            raise ClucsoError(rc, "clusco_create")
+        _handles[device] = h
+    return h
+
+
+def _check(rc, h, what):
+    if rc != OK:
+        detail = lib().clusco_last_error(h)
+        raise ClucsoError(rc, what, detail.decode() if detail else "")
+
+
+def _prec(p) -> int:
+    if isinstance(p, int):
+        return p
+    try:
+        return PRECISION[p]
+    except KeyError:
+        raise ValueError(f"unknown precision {p!r}; use one of {sorted(PRECISION)}") from None
+
+
+def _coords(x: torch.Tensor, name="coords") -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float32 or x.dim() != 3 or x.shape[2] != 3:
+        raise TypeError(f"{name} must be float32 [N, L, 3], got {x.dtype} {tuple(x.shape)}")
+    return x.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes: int, device, ws: torch.Tensor | None):
+    if ws is not None and ws.numel() >= nbytes and ws.device == device:
+        return ws
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def set_tolerance(precision, tol: float, device: int = 0):
+    """Fix-up tolerance (A) for a precision; tol <= 0 disables the FP64 fix-up."""
+    h = handle(device)
+    _check(lib().clusco_set_tolerance(h, _prec(precision), float(tol)), h, "clusco_set_tolerance")
+
+
+def workspace_size(N: int, L: int, precision="fp32", device: int = 0) -> int:
+    return int(lib().clusco_crmsd_workspace_size(handle(device), N, L, _prec(precision)))
+
+
+def crmsd_matrix(x: torch.Tensor, precision="fp32", out: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Packed all-vs-all cRMSD [N(N-1)/2] of x [N, L, 3] (float32, on the GPU)."""
+    x = _coords(x)
+    N, L = x.shape[0], x.shape[1]
+    dev = x.device
+    h = handle(dev.index)
+    p = _prec(precision)
+    need = int(lib().clusco_crmsd_workspace_size(h, N, L, p))
+    if need == 0:
+        raise ClucsoError(ERR_INVALID_ARG, "clusco_crmsd_workspace_size", f"N={N} L={L}")
+    ws = _workspace(need, dev, ws)
+    P = N * (N - 1) // 2
+    if out is None:
+        out = torch.empty(P, dtype=torch.float32, device=dev)
+    elif out.numel() != P or out.dtype != torch.float32 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float32 tensor of N(N-1)/2 elements")
+    rc = lib().clusco_crmsd_matrix(h, _ptr(x), N, L, p, _ptr(out), _ptr(ws), ws.numel(),
+                                   _stream(dev))
+    _check(rc, h, "clusco_crmsd_matrix")
+    return out
+
+
+def fixup_count(ws: torch.Tensor) -> int:
+    """32x32 pair blocks the last forward on this workspace sent to the FP64 fix-up."""
+    h = handle(ws.device.index)
+    n = ctypes.c_int64()
+    _check(lib().clusco_fixup_count(h, _ptr(ws), ctypes.byref(n), _stream(ws.device)), h,
+           "clusco_fixup_count")
+    return int(n.value)

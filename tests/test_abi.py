@@ -1,0 +1,104 @@
+"""C-ABI contract on the CPU: the library loads, exports every function the
+header declares, sizes workspaces, and rejects bad arguments with the
+documented status before anything is enqueued.  Every call here fails
+validation (or is a documented no-op), so nothing touches a device; the
+pointers passed are never dereferenced."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1302_4000_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "clusco.h")
+FAKE = ctypes.c_void_p(0x10000)        # never dereferenced
+FAKE_ODD = ctypes.c_void_p(0x10002)
+
+
+def declared_functions():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(clusco_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(binding.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return binding.lib()
+
+
+@pytest.fixture(scope="module")
+def h(L):
+    hh = ctypes.c_void_p()
+    assert L.clusco_create(ctypes.byref(hh), 0) == binding.OK
+    yield hh
+    L.clusco_destroy(hh)
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    for s, name in enumerate(["CLUSCO_OK", "CLUSCO_ERR_INVALID_ARG", "CLUSCO_ERR_WORKSPACE",
+                              "CLUSCO_ERR_UNSUPPORTED", "CLUSCO_ERR_HIP"]):
+        assert L.clusco_status_string(s).decode() == name
+
+
+def test_create_rejects_bad_arguments(L):
+    assert L.clusco_create(None, 0) == binding.ERR_INVALID_ARG
+    hh = ctypes.c_void_p()
+    assert L.clusco_create(ctypes.byref(hh), -1) == binding.ERR_INVALID_ARG
+
+
+def test_workspace_sizes(L, h):
+    s1 = L.clusco_crmsd_workspace_size(h, 200, 100, 0)
+    s2 = L.clusco_crmsd_workspace_size(h, 20000, 150, 1)
+    assert s1 > 0 and s2 > s1 and s1 % 256 == 0 and s2 % 256 == 0
+    # operands alone: 3 planes x Np x Lp (FP32) / two halves per value (split)
+    assert s1 >= 3 * 256 * 104 * 4
+    assert s2 >= 2 * 2 * 3 * 20032 * 160
+    assert L.clusco_crmsd_workspace_size(h, 10, 0, 0) == 0
+    assert L.clusco_crmsd_workspace_size(h, -1, 5, 0) == 0
+    assert L.clusco_crmsd_workspace_size(h, 10, 5, 9) == 0
+    assert L.clusco_crmsd_workspace_size(None, 10, 5, 0) == 0
+
+
+def test_matrix_argument_errors(L, h):
+    f = L.clusco_crmsd_matrix
+    need = L.clusco_crmsd_workspace_size(h, 100, 50, 0)
+    assert f(None, FAKE, 100, 50, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 0, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, -3, 50, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, 7, FAKE, FAKE, need, None) == binding.ERR_UNSUPPORTED
+    assert f(h, None, 100, 50, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, 0, None, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE_ODD, 100, 50, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, 0, FAKE, None, need, None) == binding.ERR_WORKSPACE
+    assert f(h, FAKE, 100, 50, 0, FAKE, FAKE, need - 1, None) == binding.ERR_WORKSPACE
+    assert f(h, FAKE, 100, 50, 0, FAKE, ctypes.c_void_p(0x10040), need, None) == \
+        binding.ERR_INVALID_ARG
+    assert b"256" in L.clusco_last_error(h)
+    assert f(h, FAKE, 1 << 21, 50, 0, FAKE, FAKE, need, None) == binding.ERR_UNSUPPORTED
+    # N in {0, 1}: nothing to compute, nothing enqueued, pointers unused
+    assert f(h, None, 0, 50, 0, None, None, 0, None) == binding.OK
+    assert f(h, None, 1, 50, 3, None, None, 0, None) == binding.OK
+
+
+def test_set_tolerance(L, h):
+    assert L.clusco_set_tolerance(h, 0, 1e-4) == binding.OK
+    assert L.clusco_set_tolerance(h, 11, 1e-4) == binding.ERR_UNSUPPORTED
+    assert L.clusco_set_tolerance(None, 0, 1e-4) == binding.ERR_INVALID_ARG
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    from paper_1302_4000_amd import crmsd_matrix
+    with pytest.raises(TypeError):
+        crmsd_matrix(torch.zeros(4, 5, 3))

@@ -1,0 +1,152 @@
+"""GPU parity of the all-vs-all forward against the FP64 oracle.
+
+Each test prints what it runs before touching the GPU.  Tolerances (A, max
+absolute error) are the ones include/clusco.h states per precision.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_4000_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "fp64": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def cl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1302_4000_amd as m
+    for p, t in (("fp32", 1e-4), ("bf16", 5e-4), ("fp16", 1e-4), ("fp64", 1e-6)):
+        m.set_tolerance(p, t)
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run(cl, x, prec):
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    out = cl.crmsd_matrix(xd, prec)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp64"])
+def test_n200_l100_all_pairs(cl, prec):
+    say(f"[parity] N=200 L=100 all pairs, {prec}")
+    x = synth.workload("n200_l100")
+    want = oracle.crmsd_matrix(x)
+    got = run(cl, x, prec).cpu().numpy().astype(np.float64)
+    err = np.abs(got - want)
+    say(f"  max err {err.max():.3e} A, mean {err.mean():.3e}")
+    assert err.max() < TOL[prec]
+
+
+@pytest.mark.parametrize("N,L", [(2, 7), (3, 1), (5, 2), (7, 3), (33, 17), (65, 33), (77, 5),
+                                 (130, 150), (129, 64), (64, 16), (96, 255)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_ragged_shapes(cl, N, L, prec):
+    say(f"[parity] ragged N={N} L={L} {prec}")
+    x = synth.make_ensemble(1000 + N + L, N, L, sigma=(0.3, 5.0))
+    want = oracle.crmsd_matrix(x)
+    got = run(cl, x, prec).cpu().numpy().astype(np.float64)
+    assert got.shape == want.shape
+    if L == 1:
+        assert np.all(got == 0.0)
+    assert np.abs(got - want).max() < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_degenerate_models(cl, prec):
+    say(f"[parity] degenerate models {prec}")
+    rng = np.random.default_rng(0)
+    L = 40
+    A = synth.random_walk(rng, L)
+    R = synth.random_rotations(rng, 8)
+    flip = np.diag([1.0, 1.0, -1.0])
+    t = rng.normal(0, 4, L)
+    planar = np.c_[rng.normal(0, 5, (L, 2)), np.zeros(L)]
+    models = [A, A.copy(), A @ R[0].T + 3.0,           # identical and rigid copies
+              A @ flip, A @ flip @ R[1].T,              # mirror images (S = -1)
+              t[:, None] * np.array([1.0, 0, 0]),       # collinear
+              t[::-1, None] * np.array([0, 1.0, 0]) @ R[2].T,
+              planar, planar @ flip @ R[3].T,           # planar and its mirror
+              A + rng.normal(0, 0.01, A.shape),         # near-identical
+              np.zeros((L, 3)) + 5.0]                   # a single point repeated
+    x = np.stack(models).astype(np.float32)
+    want = oracle.crmsd_matrix(x)
+    got = run(cl, x, prec).cpu().numpy().astype(np.float64)
+    err = np.abs(got - want)
+    say(f"  max err {err.max():.3e}")
+    assert err.max() < TOL[prec]
+
+
+def test_empty_and_single(cl):
+    say("[parity] N=0 and N=1")
+    for N in (0, 1):
+        x = torch.zeros(N, 10, 3, device="cuda")
+        assert cl.crmsd_matrix(x).numel() == 0
+
+
+def test_deterministic(cl):
+    say("[parity] determinism N=300 L=90")
+    x = synth.make_ensemble(5, 300, 90)
+    a = run(cl, x, "bf16").cpu()
+    b = run(cl, x, "bf16").cpu()
+    assert torch.equal(a, b)
+
+
+def sample_check(cl, x, prec, I, J, label):
+    N = x.shape[0]
+    out = run(cl, x, prec)
+    k = torch.from_numpy(oracle.packed_index(I, J, N)).cuda()
+    got = out[k].cpu().numpy().astype(np.float64)
+    want = oracle.crmsd_pairs(x, I, J)
+    err = np.abs(got - want)
+    say(f"  {label}: {len(I)} pairs, max err {err.max():.3e} A at oracle "
+        f"{want[int(np.argmax(err))]:.3f} A")
+    return err, want
+
+
+def random_pairs(rng, N, n, lo=0, hi=None):
+    hi = N if hi is None else hi
+    i = rng.integers(lo, hi, n)
+    j = rng.integers(0, N, n)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    return np.minimum(i, j), np.maximum(i, j)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_n5000_l300_sampled(cl, prec):
+    say(f"[parity] N=5000 L=300 sampled, {prec}")
+    x = synth.workload("n5000_l300")
+    rng = np.random.default_rng(42)
+    I, J = random_pairs(rng, 5000, 20000)
+    # complete first and last rows of the packed triangle
+    I = np.r_[I, np.zeros(4999, np.int64), np.arange(4999)]
+    J = np.r_[J, np.arange(1, 5000), np.full(4999, 4999)]
+    err, _ = sample_check(cl, x, prec, I, J, "random+edge rows")
+    assert err.max() < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_n20000_l150_sampled(cl, prec):
+    say(f"[parity] N=20000 L=150 sampled, {prec}")
+    x = synth.workload("n20000_l150")
+    rng = np.random.default_rng(7)
+    I, J = random_pairs(rng, 20000, 100000)
+    err, _ = sample_check(cl, x, prec, I, J, "uniform 1e5")
+    assert err.max() < TOL[prec]
+    ii, jj = np.triu_indices(50, 1)
+    err, _ = sample_check(cl, x, prec, ii, jj, "near-identical 1225")
+    assert err.max() < TOL[prec]
+    I2 = rng.integers(0, 50, 10000)
+    J2 = rng.integers(50, 20000, 10000)
+    err, _ = sample_check(cl, x, prec, I2, J2, "near-vs-bulk 1e4")
+    assert err.max() < TOL[prec]
