@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark of the all-vs-all cRMSD hot path on one MI355X.
+
+One step = one full pass of the hot path over the N=20,000 x L=150 ensemble
+(prep -> fused MFMA contraction + FP64 Eq. 2 epilogue + packed store ->
+FP64 fix-up), split-BF16 precision by default, inputs already resident in
+HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
+
+The roofline entry is for the dominant kernel (the fused tile kernel): its
+average duration is measured live with HIP events recorded by the library on
+the stream it launches on; achieved = algorithmic flops per launch (18 L per
+pair: nine length-L dot products, FMA = 2 flops) / that duration.  HBM
+traffic comes from a committed rocprofv3 counter summary under profiles/ and
+is reported only while the kernel sources still match the hash recorded
+there.
+
+The CPU baseline is the FP64 oracle timed on this host's cores on a bounded
+sample of the same workload (the all-vs-all of its first n models), and the
+maximum error of the GPU scores is measured against the same oracle on a
+sample of pairs; both run outside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("all-vs-all cRMSD pairs/s (N=20k,L=150); MFMA util; max err vs FP64 oracle (Å)")
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp64": 78.6}
+HBM_PEAK_GBS = 8000.0
+KBLOCK = {"fp32": 8, "bf16": 16, "fp16": 16, "fp64": 1}
+KERNEL_SOURCES = ["paper_1302_4000_amd/csrc/tile.hip", "paper_1302_4000_amd/csrc/eq2.h",
+                  "paper_1302_4000_amd/csrc/internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(prec: str, workload: str):
+    """HBM bytes per tile-kernel launch from a committed counter summary, or
+    None when there is none or the kernel changed since it was taken."""
+    pat = os.path.join(ROOT, "profiles", f"tile_{prec}_{workload}_hbm_traffic.md")
+    for f in glob.glob(pat):
+        txt = open(f).read()
+        m_h = re.search(r"source-sha256:\s*([0-9a-f]+)", txt)
+        m_b = re.search(r"traffic-bytes-per-launch:\s*([0-9.eE+]+)", txt)
+        if m_h and m_b and m_h.group(1) == kernel_hash():
+            return float(m_b.group(1))
+    return None
+
+
+def issued_mfma_flops(prec: str, N: int, L: int) -> float:
+    """MFMA flops the tile kernel issues: every 32x32 pair block of the upper
+    triangle of 64x64 tiles, padded K, and three products in split modes."""
+    kb = KBLOCK[prec]
+    Lp = -(-L // kb) * kb
+    Np = -(-N // 64) * 64
+    nb = Np // 64
+    T = nb * (nb + 1) // 2
+    waves = 4 * T - nb          # the wave below the diagonal of a diagonal tile idles
+    prod = 3 if prec in ("bf16", "fp16") else 1
+    return waves * 32 * 32 * 9 * Lp * 2.0 * prod
+
+
+def time_path(cl, torch, x, prec, steps, warmup):
+    N, L = x.shape[0], x.shape[1]
+    P = N * (N - 1) // 2
+    out = torch.empty(P, dtype=torch.float32, device=x.device)
+    ws = torch.empty(cl.workspace_size(N, L, prec), dtype=torch.uint8, device=x.device)
+    for _ in range(warmup):
+        cl.crmsd_matrix(x, prec, out=out, ws=ws)
+    torch.cuda.synchronize()
+    dev = x.device.index
+    cl.binding.stage_timing(dev, steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cl.crmsd_matrix(x, prec, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, ncalls = cl.binding.stage_times(dev)
+    cl.binding.stage_timing(dev, 0)
+    assert ncalls == steps
+    ms = (t1 - t0) * 1e3 / steps
+    return dict(ms_per_step=ms, pairs_per_s=P / (ms * 1e-3),
+                prep_ms=stage_ms[0] / steps, tile_ms=stage_ms[1] / steps,
+                fixup_ms=stage_ms[2] / steps, fixup_blocks=cl.fixup_count(ws)), out
+
+
+def oracle_leg(x_np, outs, want_cpu, threads):
+    """Maximum error of GPU scores vs the FP64 oracle on a pair sample, and
+    the oracle's own throughput on a bounded sample of the workload."""
+    import numpy as np
+    import torch
+
+    import oracle
+    N = x_np.shape[0]
+    rng = np.random.default_rng(7)
+    i = rng.integers(0, N, 100000)
+    j = rng.integers(0, N, 100000)
+    keep = i != j
+    I, J = np.minimum(i, j)[keep], np.maximum(i, j)[keep]
+    ii, jj = np.triu_indices(min(50, N), 1)
+    I2 = rng.integers(0, min(50, N), 10000)
+    J2 = rng.integers(min(50, N), N, 10000)
+    strata = {"uniform_1e5": (I, J), "near_identical_1225": (ii, jj), "near_vs_bulk_1e4": (I2, J2)}
+    errs = {}
+    for prec, out in outs.items():
+        e = {}
+        for name, (a, b) in strata.items():
+            k = torch.from_numpy(oracle.packed_index(a, b, N)).to(out.device)
+            got = out[k].cpu().numpy().astype(np.float64)
+            ref = oracle.crmsd_pairs(x_np, a, b, threads=threads)
+            e[name] = float(np.abs(got - ref).max())
+        e["max"] = max(e.values())
+        errs[prec] = e
+    cpu = None
+    if want_cpu:
+        # bounded sample: all-vs-all of the first n models, sized to ~15 s
+        n0 = min(N, 400)
+        t = time.perf_counter()
+        oracle.crmsd_matrix(x_np[:n0], threads=threads)
+        rate = n0 * (n0 - 1) / 2 / (time.perf_counter() - t)
+        n = int(min(N, max(n0, (2 * rate * 15.0) ** 0.5)))
+        t = time.perf_counter()
+        oracle.crmsd_matrix(x_np[:n], threads=threads)
+        dt = time.perf_counter() - t
+        pairs = n * (n - 1) // 2
+        cpu = {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"all-vs-all of the first {n} models of the same ensemble "
+                         f"({pairs} pairs, {dt:.1f} s, FP64 explicit Kabsch, OpenMP)"}
+    return errs, cpu
+
+
+def copy_calibration(nbytes: int):
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--workload", default="n20000_l150")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true", help="skip the oracle error sample")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32-path comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the all-vs-all cRMSD kernels run on a single "
+              "MI355X; multi-GPU sharding is a design note only (run with --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_1302_4000_amd as cl
+    from paper_1302_4000_amd import synth
+
+    log(f"[bench] generating {args.workload}")
+    x_np = synth.workload(args.workload)
+    N, L = x_np.shape[0], x_np.shape[1]
+    P = N * (N - 1) // 2
+    x = torch.from_numpy(x_np).cuda()
+    torch.cuda.synchronize()
+
+    prec = args.precision
+    log(f"[bench] {prec}: warmup {args.warmup}, steps {args.steps}")
+    main_res, main_out = time_path(cl, torch, x, prec, args.steps, args.warmup)
+    log(f"[bench] {prec}: {main_res}")
+    outs = {prec: main_out}
+    cmp = None
+    if not args.no_compare and prec != "fp32":
+        steps = max(2, args.steps // 3)
+        log(f"[bench] fp32 comparison: steps {steps}")
+        cmp_res, cmp_out = time_path(cl, torch, x, "fp32", steps, 1)
+        log(f"[bench] fp32: {cmp_res}")
+        fl = issued_mfma_flops("fp32", N, L)
+        cmp = dict(cmp_res, steps=steps,
+                   mfma_util=fl / (cmp_res["tile_ms"] * 1e-3) / (PEAK_TFLOPS["fp32"] * 1e12),
+                   algorithmic_tflops=18.0 * L * P / (cmp_res["tile_ms"] * 1e-3) / 1e12)
+        outs["fp32"] = cmp_out
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    errs, cpu = (None, None)
+    if not (args.no_error and args.no_cpu_baseline):
+        log(f"[bench] oracle leg on {threads} host threads")
+        errs, cpu = oracle_leg(x_np, outs if not args.no_error else {}, not args.no_cpu_baseline,
+                               threads)
+
+    tile_s = main_res["tile_ms"] * 1e-3
+    alg = 18.0 * L * P
+    achieved = alg / tile_s / 1e12
+    issued = issued_mfma_flops(prec, N, L)
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic_from_profiles(prec, args.workload),
+            "kernel": f"tile_kernel<{prec}>", "kernel_ms": main_res["tile_ms"],
+            "issued_mfma_tflops": issued / tile_s / 1e12,
+            "mfma_util": issued / tile_s / (PEAK_TFLOPS[prec] * 1e12),
+            "effective_vs_fp32_peak": achieved / PEAK_TFLOPS["fp32"],
+            "output_hbm_gbs": 4.0 * P / tile_s / 1e9,
+            "source_sha256": kernel_hash()}
+    line = {
+        "metric": METRIC, "value": main_res["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": args.workload, "N": N, "L": L, "pairs": P,
+                   "precision": {"bf16": "split_bf16x3", "fp16": "split_fp16x3",
+                                 "fp32": "fp32"}[prec],
+                   "epilogue": "fp64", "parallelism": "single_gpu"},
+        "stages_ms": {k: main_res[k] for k in ("prep_ms", "tile_ms", "fixup_ms")},
+        "fixup_blocks": main_res["fixup_blocks"],
+        "roofline": roof,
+        "max_err_A": errs,
+        "fp32_path": cmp,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

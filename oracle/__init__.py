@@ -59,8 +59,10 @@ def _load():
     lib.oracle_crmsd_grad_pair.argtypes = [dp, dp, i64, dp, dp, dp]
     lib.oracle_crmsd_matrix_grad.argtypes = [dp, i64, i64, dp, dp, cint]
     lib.oracle_crmsd_cross_grad.argtypes = [dp, i64, dp, i64, i64, dp, dp, dp, cint]
+    lib.oracle_crmsd_matrix_grad_rows.argtypes = [dp, i64, i64, dp, lp, i64, dp, cint]
     for f in ("oracle_crmsd_matrix", "oracle_crmsd_pairs", "oracle_crmsd_cross",
-              "oracle_crmsd_grad_pair", "oracle_crmsd_matrix_grad", "oracle_crmsd_cross_grad"):
+              "oracle_crmsd_grad_pair", "oracle_crmsd_matrix_grad", "oracle_crmsd_cross_grad",
+              "oracle_crmsd_matrix_grad_rows"):
         getattr(lib, f).restype = cint
     _lib = lib
     return lib
@@ -147,6 +149,18 @@ def crmsd_matrix_grad(x, g, threads: int = 0) -> np.ndarray:
     out = np.zeros_like(x)
     _check(_load().oracle_crmsd_matrix_grad(_p(x), N, x.shape[1], _p(g), _p(out), threads),
            "crmsd_matrix_grad")
+    return out
+
+
+def crmsd_matrix_grad_rows(x, g, rows, threads: int = 0) -> np.ndarray:
+    """Rows `rows` of crmsd_matrix_grad(x, g), shape [len(rows), L, 3]."""
+    x, g = _d(x), _d(g)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros((rows.shape[0], x.shape[1], 3))
+    lp = ctypes.POINTER(ctypes.c_int64)
+    _check(_load().oracle_crmsd_matrix_grad_rows(_p(x), x.shape[0], x.shape[1], _p(g),
+                                                 rows.ctypes.data_as(lp), rows.shape[0],
+                                                 _p(out), threads), "crmsd_matrix_grad_rows")
     return out
 
 

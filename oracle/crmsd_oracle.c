@@ -355,6 +355,40 @@ int oracle_crmsd_matrix_grad(const double *X, int64_t N, int64_t L, const double
     return 0;
 }
 
+/* The same gradient for selected models only: out[r][L][3] is the row of
+ * model rows[r] (for checking a large ensemble on a sample of models). */
+int oracle_crmsd_matrix_grad_rows(const double *X, int64_t N, int64_t L, const double *g,
+                                  const int64_t *rows, int64_t R, double *out, int nthreads)
+{
+    if (N < 0 || L < 1 || R < 0) return 1;
+    for (int64_t r = 0; r < R; ++r)
+        if (rows[r] < 0 || rows[r] >= N) return 2;
+    set_threads(nthreads);
+    memset(out, 0, sizeof(double) * 3 * L * R);
+#pragma omp parallel
+    {
+        double *a = malloc(sizeof(double) * 6 * L), *b = a + 3 * L;
+#pragma omp for schedule(dynamic, 16) collapse(2)
+        for (int64_t r = 0; r < R; ++r) {
+            for (int64_t j = 0; j < N; ++j) {
+                const int64_t i = rows[r];
+                if (j == i) continue;
+                int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+                double gk = g[lo * (2 * N - lo - 1) / 2 + hi - lo - 1];
+                double *tmp = calloc((size_t)(3 * L), sizeof(double));
+                centre(X + 3 * L * i, L, a);
+                centre(X + 3 * L * j, L, b);
+                add_grad_first(a, b, L, gk, tmp);
+#pragma omp critical
+                for (int64_t t = 0; t < 3 * L; ++t) out[3 * L * r + t] += tmp[t];
+                free(tmp);
+            }
+        }
+        free(a);
+    }
+    return 0;
+}
+
 /* Cross gradient: gradA[Na][L][3], gradB[Nb][L][3] (overwritten) of
  * sum_{ia,ib} g[ia][ib] cRMSD(A_ia, B_ib). */
 int oracle_crmsd_cross_grad(const double *A, int64_t Na, const double *B, int64_t Nb, int64_t L,

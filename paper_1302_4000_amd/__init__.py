@@ -5,8 +5,12 @@ C ABI of ``include/clusco.h``); this package is its thin Python binding.
 Importing the package does not load the library: the first call does, and
 raises if it is not built.
 """
-from .binding import (ClucsoError, PRECISION, crmsd_matrix, fixup_count, set_tolerance,  # noqa: F401
-                      workspace_size)
+from .autograd import CRMSDCross, CRMSDMatrix, crmsd_cross_ad, crmsd_matrix_ad  # noqa: F401
+from .binding import (Batch, ClucsoError, PRECISION, batched_workspace_size,  # noqa: F401
+                      crmsd_backward, crmsd_batched, crmsd_cross, crmsd_cross_backward,
+                      crmsd_matrix, fixup_count, set_tolerance, workspace_size)
 
-__all__ = ["ClucsoError", "PRECISION", "crmsd_matrix", "fixup_count", "set_tolerance",
-           "workspace_size"]
+__all__ = ["Batch", "CRMSDCross", "CRMSDMatrix", "ClucsoError", "PRECISION",
+           "batched_workspace_size", "crmsd_backward", "crmsd_batched", "crmsd_cross",
+           "crmsd_cross_ad", "crmsd_cross_backward", "crmsd_matrix", "crmsd_matrix_ad",
+           "fixup_count", "set_tolerance", "workspace_size"]

@@ -57,6 +57,9 @@ def lib():
             "clusco_crmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_fixup_count": (st, [vp, vp, i64p, vp]),
+            "clusco_stage_timing": (st, [vp, ctypes.c_int]),
+            "clusco_stage_times": (st, [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int)]),
             "clusco_crmsd_batched_workspace_size": (sz, [vp, i32, i64p, i64p, st]),
             "clusco_crmsd_batched": (st, [vp, i32, i64p, i64p, i64p, i64p, vp, st, vp, vp, sz, vp]),
             "clusco_crmsd_cross_workspace_size": (sz, [vp, i64, i64, i64, st]),
@@ -163,3 +166,163 @@ def fixup_count(ws: torch.Tensor) -> int:
     _check(lib().clusco_fixup_count(h, _ptr(ws), ctypes.byref(n), _stream(ws.device)), h,
            "clusco_fixup_count")
     return int(n.value)
+
+
+def stage_timing(device: int, max_calls: int):
+    """Record HIP events around the stages of the next max_calls forward calls."""
+    h = handle(device)
+    _check(lib().clusco_stage_timing(h, int(max_calls)), h, "clusco_stage_timing")
+
+
+def stage_times(device: int):
+    """([prep, contraction+epilogue, fix-up] summed ms, calls) since the last read."""
+    h = handle(device)
+    ms = (ctypes.c_double * 3)()
+    n = ctypes.c_int()
+    _check(lib().clusco_stage_times(h, ms, ctypes.byref(n)), h, "clusco_stage_times")
+    return [ms[k] for k in range(3)], n.value
+
+
+def crmsd_cross(a: torch.Tensor, b: torch.Tensor, precision="fp32",
+                out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Dense cRMSD [Na, Nb] between a [Na, L, 3] and b [Nb, L, 3] (Nb = 1: every
+    model against one reference)."""
+    a = _coords(a, "a")
+    b = _coords(b, "b")
+    if a.shape[1] != b.shape[1] or a.device != b.device:
+        raise TypeError("a and b need the same L and device")
+    Na, Nb, L = a.shape[0], b.shape[0], a.shape[1]
+    dev = a.device
+    h = handle(dev.index)
+    p = _prec(precision)
+    need = int(lib().clusco_crmsd_cross_workspace_size(h, Na, Nb, L, p))
+    if need == 0:
+        raise ClucsoError(ERR_INVALID_ARG, "clusco_crmsd_cross_workspace_size")
+    ws = _workspace(need, dev, ws)
+    if out is None:
+        out = torch.empty(Na, Nb, dtype=torch.float32, device=dev)
+    elif out.numel() != Na * Nb or out.dtype != torch.float32 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float32 tensor of Na*Nb elements")
+    rc = lib().clusco_crmsd_cross(h, _ptr(a), Na, _ptr(b), Nb, L, p, _ptr(out), _ptr(ws),
+                                  ws.numel(), _stream(dev))
+    _check(rc, h, "clusco_crmsd_cross")
+    return out
+
+
+def _i64(arr):
+    import numpy as np
+    a = np.ascontiguousarray(arr, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+class Batch:
+    """Shapes and offsets of E ensembles stored back to back in one float32
+    buffer; packed outputs back to back in another."""
+
+    def __init__(self, shapes):
+        import numpy as np
+        self.shapes = [(int(n), int(l)) for n, l in shapes]
+        self.N = np.array([n for n, _ in self.shapes], dtype=np.int64)
+        self.L = np.array([l for _, l in self.shapes], dtype=np.int64)
+        sizes = self.N * self.L * 3
+        self.coord_off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        pairs = self.N * (self.N - 1) // 2
+        self.out_off = np.concatenate([[0], np.cumsum(pairs)[:-1]]).astype(np.int64)
+        self.n_coords = int(sizes.sum())
+        self.n_out = int(pairs.sum())
+
+    def pack(self, ensembles, device):
+        flat = torch.cat([e.reshape(-1) for e in ensembles]) if ensembles else \
+            torch.empty(0, dtype=torch.float32)
+        return flat.to(device=device, dtype=torch.float32).contiguous()
+
+    def split(self, out):
+        return [out[o:o + n * (n - 1) // 2] for o, (n, _) in zip(self.out_off, self.shapes)]
+
+
+def batched_workspace_size(batch: Batch, precision="fp32", device: int = 0) -> int:
+    _, pN = _i64(batch.N)
+    _, pL = _i64(batch.L)
+    return int(lib().clusco_crmsd_batched_workspace_size(handle(device), len(batch.shapes), pN,
+                                                         pL, _prec(precision)))
+
+
+def crmsd_batched(batch: Batch, coords: torch.Tensor, precision="fp32",
+                  out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """All-vs-all cRMSD of every ensemble of `batch`; coords is the flat float32
+    buffer of all models (Batch.pack).  Returns the flat packed output
+    (Batch.split gives the per-ensemble views)."""
+    if not isinstance(coords, torch.Tensor) or not coords.is_cuda or coords.dtype != torch.float32:
+        raise TypeError("coords must be a float32 CUDA tensor")
+    coords = coords.contiguous()
+    if coords.numel() < batch.n_coords:
+        raise TypeError("coords holds fewer values than the batch needs")
+    dev = coords.device
+    h = handle(dev.index)
+    p = _prec(precision)
+    E = len(batch.shapes)
+    aN, pN = _i64(batch.N)
+    aL, pL = _i64(batch.L)
+    aC, pC = _i64(batch.coord_off)
+    aO, pO = _i64(batch.out_off)
+    need = int(lib().clusco_crmsd_batched_workspace_size(h, E, pN, pL, p))
+    if need == 0 and E > 0:
+        raise ClucsoError(ERR_INVALID_ARG, "clusco_crmsd_batched_workspace_size")
+    ws = _workspace(need, dev, ws)
+    if out is None:
+        out = torch.empty(batch.n_out, dtype=torch.float32, device=dev)
+    elif out.numel() < batch.n_out or out.dtype != torch.float32 or not out.is_contiguous():
+        raise TypeError("out too small")
+    rc = lib().clusco_crmsd_batched(h, E, pN, pL, pC, pO, _ptr(coords), p, _ptr(out), _ptr(ws),
+                                    ws.numel(), _stream(dev))
+    _check(rc, h, "clusco_crmsd_batched")
+    return out
+
+
+def crmsd_backward(x: torch.Tensor, rmsd: torch.Tensor, grad_out: torch.Tensor,
+                   precision="fp32", grad: torch.Tensor | None = None,
+                   ws: torch.Tensor | None = None) -> torch.Tensor:
+    """d/dx of sum_k grad_out[k] * rmsd_k for the packed all-vs-all scores."""
+    x = _coords(x)
+    N, L = x.shape[0], x.shape[1]
+    P = N * (N - 1) // 2
+    if rmsd.numel() != P or grad_out.numel() != P:
+        raise TypeError("rmsd and grad_out must hold N(N-1)/2 values")
+    rmsd = rmsd.to(torch.float32).contiguous()
+    grad_out = grad_out.to(torch.float32).contiguous()
+    dev = x.device
+    h = handle(dev.index)
+    p = _prec(precision)
+    need = int(lib().clusco_crmsd_backward_workspace_size(h, N, L, p))
+    ws = _workspace(need, dev, ws)
+    if grad is None:
+        grad = torch.empty_like(x)
+    rc = lib().clusco_crmsd_backward(h, _ptr(x), N, L, _ptr(rmsd), _ptr(grad_out), p, _ptr(grad),
+                                     _ptr(ws), ws.numel(), _stream(dev))
+    _check(rc, h, "clusco_crmsd_backward")
+    return grad
+
+
+def crmsd_cross_backward(a: torch.Tensor, b: torch.Tensor, rmsd: torch.Tensor,
+                         grad_out: torch.Tensor, precision="fp32", need_b: bool = True,
+                         ws: torch.Tensor | None = None):
+    """(d/da, d/db) of sum grad_out[ia, ib] * rmsd[ia, ib] for the dense cross scores."""
+    a = _coords(a, "a")
+    b = _coords(b, "b")
+    Na, Nb, L = a.shape[0], b.shape[0], a.shape[1]
+    if rmsd.numel() != Na * Nb or grad_out.numel() != Na * Nb:
+        raise TypeError("rmsd and grad_out must hold Na*Nb values")
+    rmsd = rmsd.to(torch.float32).contiguous()
+    grad_out = grad_out.to(torch.float32).contiguous()
+    dev = a.device
+    h = handle(dev.index)
+    p = _prec(precision)
+    need = int(lib().clusco_crmsd_cross_backward_workspace_size(h, Na, Nb, L, p))
+    ws = _workspace(need, dev, ws)
+    ga = torch.empty_like(a)
+    gb = torch.empty_like(b) if need_b else None
+    rc = lib().clusco_crmsd_cross_backward(h, _ptr(a), Na, _ptr(b), Nb, L, _ptr(rmsd),
+                                           _ptr(grad_out), p, _ptr(ga), _ptr(gb), _ptr(ws),
+                                           ws.numel(), _stream(dev))
+    _check(rc, h, "clusco_crmsd_cross_backward")
+    return ga, gb

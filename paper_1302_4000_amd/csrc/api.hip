@@ -1,25 +1,54 @@
 // C-ABI entry points (include/clusco.h): argument validation, workspace
 // layout and the launch sequence.  Every argument error is caught here,
-// before anything is enqueued; nothing here allocates device memory or
-// synchronises the host (clusco_fixup_count excepted).
+// before anything is enqueued.  Nothing on the per-call path allocates
+// device memory or synchronises the host; the first batched call for a new
+// shape uploads its plan (a small device table) once.
 #include <string.h>
 
+#include <algorithm>
+#include <list>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
 using namespace clusco;
+
+namespace {
+
+struct BatchPlan {
+    // key
+    std::vector<int64_t> key;
+    // device tables: ModelSet[nset] then Problem[nprob]
+    void *dtab = nullptr;
+    int32_t nset = 0, nprob = 0;
+    int64_t total_models = 0, T = 0, n_wtiles = 0;
+    size_t ws_total = 0, off_list = 0;
+    Problem first{};          // any problem (for launches with one)
+    // cached graph for the last buffers it was captured with
+    hipGraphExec_t exec = nullptr;
+    const void *g_coords = nullptr, *g_out = nullptr, *g_ws = nullptr;
+};
+
+} // namespace
 
 struct clusco_ctx {
     int device;
     double tol[4];   // fix-up tolerance per precision (A); <= 0 disables
     double eps[4];   // calibrated relative error of the contraction per precision
     std::string last_error;
+    // stage timing (measurement only): 4 events per recorded call
+    std::vector<hipEvent_t> events;
+    int slots = 0, used = 0;
+    // batched plans, most recent first
+    std::list<BatchPlan> plans;
+    hipStream_t capture = nullptr;
 };
 
 namespace {
 
-constexpr int64_t MAX_N = 1 << 20;   // packed list entries hold 16-bit row blocks
+constexpr int64_t MAX_N = 1 << 20;   // fix-up entries hold 16-bit row blocks
+constexpr size_t MAX_PLANS = 8;
 
 clusco_status fail(clusco_handle h, clusco_status s, const char *msg)
 {
@@ -73,9 +102,369 @@ struct DeviceGuard {
 double flag_coef(clusco_handle h, int mode, int64_t L)
 {
     const double tol = h->tol[mode];
-    if (!(tol > 0.0)) return -1.0;
+    if (mode == MODE_FP64 || !(tol > 0.0)) return -1.0;
     // flag when  eps (E_i + E_j) / (L score) > tol / 2
     return 2.0 * h->eps[mode] / ((double)L * tol);
+}
+
+void stage_mark(clusco_handle h, int k, hipStream_t s)
+{
+    if (h->used >= h->slots) return;
+    (void)hipEventRecord(h->events[4 * h->used + k], s);
+    if (k == 3) ++h->used;
+}
+
+// ---------------------------------------------------------------- layout
+
+size_t take(size_t &o, size_t bytes)
+{
+    size_t r = o;
+    o += (size_t)round_up((int64_t)bytes, 256);
+    return r;
+}
+
+ModelSet make_set(int mode, int64_t X, int64_t N, int64_t L, int64_t model0, int use_b, size_t &o)
+{
+    ModelSet s{};
+    s.X = X;
+    s.N = N;
+    s.Np = round_up(N > 0 ? N : 1, TILE);
+    s.L = L;
+    s.Lp = round_up(L, kblock(mode));
+    s.KB = s.Lp / kblock(mode);
+    s.model0 = model0;
+    s.use_b = use_b;
+    s.E = (int64_t)take(o, sizeof(double) * s.Np);
+    s.cen = (int64_t)take(o, sizeof(double) * 3 * s.Np);
+    s.ops = (int64_t)take(o, op_bytes_per_model(mode, s.Lp) * s.Np);
+    return s;
+}
+
+Problem make_problem(const ModelSet &A, const ModelSet &B, int sym, double coef)
+{
+    Problem p{};
+    p.NA = A.N;
+    p.NB = B.N;
+    p.L = A.L;
+    p.KB = A.KB;
+    p.nbA = A.Np / TILE;
+    p.nbB = B.Np / TILE;
+    p.nrbA = A.Np / ROWBLK;
+    p.nrbB = B.Np / ROWBLK;
+    p.opsA = A.ops;
+    p.opsB = B.ops;
+    p.EA = A.E;
+    p.EB = B.E;
+    p.cenA = A.cen;
+    p.cenB = B.cen;
+    p.XA = A.X;
+    p.XB = B.X;
+    p.flag_coef = coef;
+    p.sym = sym;
+    return p;
+}
+
+struct SingleLayout {
+    ModelSet A, B;
+    Problem p;
+    size_t total, off_list;
+};
+
+SingleLayout single_layout(clusco_handle h, int mode, int64_t N, int64_t L)
+{
+    SingleLayout s{};
+    size_t o = 256;
+    s.A = make_set(mode, 0, N, L, 0, 0, o);
+    s.B = s.A;
+    s.p = make_problem(s.A, s.A, 1, h ? flag_coef(h, mode, L) : -1.0);
+    s.off_list = take(o, sizeof(FixEntry) * problem_wtiles(s.p));
+    s.total = o;
+    return s;
+}
+
+SingleLayout cross_layout(clusco_handle h, int mode, int64_t Na, int64_t Nb, int64_t L)
+{
+    SingleLayout s{};
+    size_t o = 256;
+    s.A = make_set(mode, 0, Na, L, 0, 0, o);
+    s.B = make_set(mode, 0, Nb, L, s.A.Np, 1, o);
+    s.p = make_problem(s.A, s.B, 0, h ? flag_coef(h, mode, L) : -1.0);
+    s.off_list = take(o, sizeof(FixEntry) * problem_wtiles(s.p));
+    s.total = o;
+    return s;
+}
+
+// The backward recomputes each pair's correlation with the forward's
+// contraction (FP32 MFMA for the FP32 and FP64 precisions) and stores one
+// 12-float record per pair after the forward layout.
+int bwd_mode(int mode) { return mode == MODE_FP64 ? MODE_FP32 : mode; }
+
+struct BwdLayout {
+    SingleLayout s;
+    size_t off_wq, total;
+};
+
+BwdLayout bwd_layout(clusco_handle h, int mode, int64_t NA, int64_t NB, int64_t L, bool cross)
+{
+    BwdLayout b{};
+    b.s = cross ? cross_layout(h, bwd_mode(mode), NA, NB, L) : single_layout(h, bwd_mode(mode), NA, L);
+    size_t o = b.s.total;
+    const int64_t pairs = cross ? NA * NB : NA * (NA - 1) / 2;
+    b.off_wq = take(o, sizeof(float) * 12 * (pairs > 0 ? pairs : 1));
+    b.total = o;
+    return b;
+}
+
+clusco_status enqueue_bwd(clusco_handle h, int mode, const float *XA, const float *XB,
+                          char *ws, const BwdLayout &b, bool cross, const float *rmsd,
+                          const float *gout, float *gradA, float *gradB, hipStream_t s)
+{
+    const int m = bwd_mode(mode);
+    PrepLaunch pl{};
+    pl.XA = XA;
+    pl.XB = XB;
+    pl.ws = ws;
+    pl.mode = m;
+    pl.counters = (int *)ws;
+    pl.set[0] = b.s.A;
+    pl.set[1] = b.s.B;
+    pl.nset = cross ? 2 : 1;
+    pl.total = b.s.A.Np + (cross ? b.s.B.Np : 0);
+    hipError_t e = launch_prep(pl, s);
+    if (e != hipSuccess) return hip_fail(h, e, "prep launch");
+    TileLaunch tl{};
+    tl.ws = ws;
+    tl.prob = b.s.p;
+    tl.nprob = 1;
+    tl.kind = cross ? TK_RECT : TK_SYM;
+    tl.T = problem_tiles(b.s.p);
+    tl.counters = (int *)ws;
+    tl.list = (FixEntry *)(ws + b.s.off_list);
+    tl.rmsd = rmsd;
+    tl.gout = gout;
+    tl.wq = (float *)(ws + b.off_wq);
+    e = launch_tile(m, tl, s, OP_BWD);
+    if (e != hipSuccess) return hip_fail(h, e, "backward pairs launch");
+    const double *cenA = (const double *)(ws + b.s.A.cen);
+    const double *cenB = (const double *)(ws + b.s.B.cen);
+    const int64_t NA = b.s.p.NA, NB = b.s.p.NB, L = b.s.p.L;
+    GradLaunch ga{XA, cross ? XB : XA, cenA, cross ? cenB : cenA, tl.wq, gradA, NA,
+                  cross ? NB : NA, L, cross ? GK_CROSS_A : GK_SYM, 0};
+    e = launch_grad(ga, s);
+    if (e != hipSuccess) return hip_fail(h, e, "gradient launch");
+    if (cross && gradB) {
+        GradLaunch gb{XB, XA, cenB, cenA, tl.wq, gradB, NB, NA, L, GK_CROSS_B, 0};
+        e = launch_grad(gb, s);
+        if (e != hipSuccess) return hip_fail(h, e, "gradient launch");
+    }
+    return CLUSCO_OK;
+}
+
+// Enqueue prep -> tile -> fix-up for the given sets / problems.
+clusco_status enqueue(clusco_handle h, int mode, const float *XA, const float *XB, char *ws,
+                      float *out, const SingleLayout *single, const BatchPlan *plan, int kind,
+                      hipStream_t s, bool timing)
+{
+    int *counters = (int *)ws;
+    PrepLaunch pl{};
+    pl.XA = XA;
+    pl.XB = XB;
+    pl.ws = ws;
+    pl.mode = mode;
+    pl.counters = counters;
+    TileLaunch tl{};
+    tl.ws = ws;
+    tl.out = out;
+    tl.kind = kind;
+    tl.counters = counters;
+    FixupLaunch fl{};
+    fl.XA = XA;
+    fl.XB = XB;
+    fl.ws = ws;
+    fl.out = out;
+    fl.counters = counters;
+    fl.all = mode == MODE_FP64;
+    double coef;
+    if (single) {
+        pl.set[0] = single->A;
+        pl.set[1] = single->B;
+        pl.nset = kind == TK_RECT ? 2 : 1;
+        pl.total = single->A.Np + (kind == TK_RECT ? single->B.Np : 0);
+        tl.prob = single->p;
+        tl.nprob = 1;
+        tl.T = problem_tiles(single->p);
+        tl.list = (FixEntry *)(ws + single->off_list);
+        fl.prob = single->p;
+        fl.nprob = 1;
+        fl.n_all = problem_wtiles(single->p);
+        fl.list = tl.list;
+        coef = single->p.flag_coef;
+    } else {
+        pl.table = (const ModelSet *)plan->dtab;
+        pl.nset = plan->nset;
+        pl.total = plan->total_models;
+        const Problem *pt = (const Problem *)((const char *)plan->dtab +
+                                              sizeof(ModelSet) * plan->nset);
+        tl.table = pt;
+        tl.nprob = plan->nprob;
+        tl.T = plan->T;
+        tl.list = (FixEntry *)(ws + plan->off_list);
+        fl.table = pt;
+        fl.nprob = plan->nprob;
+        fl.n_all = plan->n_wtiles;
+        fl.list = tl.list;
+        coef = plan->first.flag_coef;
+    }
+    if (timing) stage_mark(h, 0, s);
+    hipError_t e = launch_prep(pl, s);
+    if (e != hipSuccess) return hip_fail(h, e, "prep launch");
+    if (timing) stage_mark(h, 1, s);
+    if (mode != MODE_FP64) {
+        e = launch_tile(mode, tl, s);
+        if (e != hipSuccess) return hip_fail(h, e, "tile launch");
+    }
+    if (timing) stage_mark(h, 2, s);
+    if (mode == MODE_FP64 || coef > 0.0) {
+        e = launch_fixup(fl, s);
+        if (e != hipSuccess) return hip_fail(h, e, "fix-up launch");
+    }
+    if (timing) stage_mark(h, 3, s);
+    return CLUSCO_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+struct BatchInput {
+    int32_t E;
+    const int64_t *N, *L, *coff, *ooff;
+};
+
+std::vector<int64_t> batch_key(clusco_handle h, int mode, const BatchInput &b, bool with_offsets)
+{
+    std::vector<int64_t> k;
+    k.reserve(4 * b.E + 4);
+    k.push_back(mode);
+    k.push_back(b.E);
+    double tol = h->tol[mode], eps = h->eps[mode];
+    int64_t t, ep;
+    memcpy(&t, &tol, 8);
+    memcpy(&ep, &eps, 8);
+    k.push_back(t);
+    k.push_back(ep);
+    for (int32_t e = 0; e < b.E; ++e) {
+        k.push_back(b.N[e]);
+        k.push_back(b.L[e]);
+        if (with_offsets) {
+            k.push_back(b.coff[e]);
+            k.push_back(b.ooff[e]);
+        }
+    }
+    return k;
+}
+
+// Host-side plan: sets in input order, problems sorted by cost per tile
+// (padded length, then size) so the persistent kernel starts the longest
+// tiles first.  Returns the workspace size; fills tables when asked.
+size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<ModelSet> *sets,
+                   std::vector<Problem> *probs, size_t *off_list, int64_t *T, int64_t *nw,
+                   int64_t *total)
+{
+    size_t o = 256;
+    std::vector<ModelSet> S;
+    std::vector<Problem> P;
+    int64_t model0 = 0;
+    for (int32_t e = 0; e < b.E; ++e) {
+        if (b.N[e] < 2) continue;
+        ModelSet s = make_set(mode, b.coff ? b.coff[e] : 0, b.N[e], b.L[e], model0, 0, o);
+        model0 += s.Np;
+        S.push_back(s);
+        Problem p = make_problem(s, s, 1, flag_coef(h, mode, b.L[e]));
+        p.out = b.ooff ? b.ooff[e] : 0;
+        P.push_back(p);
+    }
+    std::stable_sort(P.begin(), P.end(), [](const Problem &x, const Problem &y) {
+        if (x.KB != y.KB) return x.KB > y.KB;
+        return x.NA > y.NA;
+    });
+    int64_t t0 = 0, w0 = 0;
+    for (Problem &p : P) {
+        p.tile0 = t0;
+        p.wtile0 = w0;
+        t0 += problem_tiles(p);
+        w0 += problem_wtiles(p);
+    }
+    size_t ol = take(o, sizeof(FixEntry) * (w0 > 0 ? w0 : 1));
+    if (sets) *sets = S;
+    if (probs) *probs = P;
+    if (off_list) *off_list = ol;
+    if (T) *T = t0;
+    if (nw) *nw = w0;
+    if (total) *total = model0;
+    return o;
+}
+
+void free_plan(BatchPlan &p)
+{
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.dtab) (void)hipFree(p.dtab);
+    p.exec = nullptr;
+    p.dtab = nullptr;
+}
+
+clusco_status get_plan(clusco_handle h, int mode, const BatchInput &b, BatchPlan **out)
+{
+    std::vector<int64_t> key = batch_key(h, mode, b, true);
+    for (auto it = h->plans.begin(); it != h->plans.end(); ++it) {
+        if (it->key == key) {
+            h->plans.splice(h->plans.begin(), h->plans, it);
+            *out = &h->plans.front();
+            return CLUSCO_OK;
+        }
+    }
+    BatchPlan p;
+    p.key = key;
+    std::vector<ModelSet> sets;
+    std::vector<Problem> probs;
+    p.ws_total = plan_layout(h, mode, b, &sets, &probs, &p.off_list, &p.T, &p.n_wtiles,
+                             &p.total_models);
+    p.nset = (int32_t)sets.size();
+    p.nprob = (int32_t)probs.size();
+    if (p.nprob > 0) {
+        p.first = probs[0];
+        const size_t bytes = sizeof(ModelSet) * sets.size() + sizeof(Problem) * probs.size();
+        std::vector<char> host(bytes);
+        memcpy(host.data(), sets.data(), sizeof(ModelSet) * sets.size());
+        memcpy(host.data() + sizeof(ModelSet) * sets.size(), probs.data(),
+               sizeof(Problem) * probs.size());
+        hipError_t e = hipMalloc(&p.dtab, bytes);
+        if (e == hipSuccess) e = hipMemcpy(p.dtab, host.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return hip_fail(h, e, "upload batch plan");
+        }
+    }
+    h->plans.push_front(std::move(p));
+    while (h->plans.size() > MAX_PLANS) {
+        free_plan(h->plans.back());
+        h->plans.pop_back();
+    }
+    *out = &h->plans.front();
+    return CLUSCO_OK;
+}
+
+clusco_status check_batch(clusco_handle h, const BatchInput &b, bool need_offsets)
+{
+    if (b.E < 0) return fail(h, CLUSCO_ERR_INVALID_ARG, "E < 0");
+    if (b.E == 0) return CLUSCO_OK;
+    if (!b.N || !b.L || (need_offsets && (!b.coff || !b.ooff)))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "null shape or offset array");
+    for (int32_t e = 0; e < b.E; ++e) {
+        if (b.N[e] < 0 || b.L[e] < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0, L >= 1");
+        if (b.N[e] > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
+        if (need_offsets && (b.coff[e] < 0 || b.ooff[e] < 0))
+            return fail(h, CLUSCO_ERR_INVALID_ARG, "negative offset");
+    }
+    return CLUSCO_OK;
 }
 
 } // namespace
@@ -112,7 +501,17 @@ clusco_status clusco_create(clusco_handle *h, int device)
     return CLUSCO_OK;
 }
 
-void clusco_destroy(clusco_handle h) { delete h; }
+void clusco_destroy(clusco_handle h)
+{
+    if (!h) return;
+    {
+        DeviceGuard g(h->device);
+        for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+        for (BatchPlan &p : h->plans) free_plan(p);
+        if (h->capture) (void)hipStreamDestroy(h->capture);
+    }
+    delete h;
+}
 
 const char *clusco_last_error(clusco_handle h) { return h ? h->last_error.c_str() : ""; }
 
@@ -127,7 +526,7 @@ clusco_status clusco_set_tolerance(clusco_handle h, clusco_precision p, double t
 size_t clusco_crmsd_workspace_size(clusco_handle h, int64_t N, int64_t L, clusco_precision p)
 {
     if (!h || N < 0 || N > MAX_N || L < 1 || !valid_precision(p)) return 0;
-    return fwd_layout(mode_of(p), N, L).total;
+    return single_layout(h, mode_of(p), N, L).total;
 }
 
 clusco_status clusco_crmsd_matrix(clusco_handle h, const float *coords, int64_t N, int64_t L,
@@ -144,51 +543,13 @@ clusco_status clusco_crmsd_matrix(clusco_handle h, const float *coords, int64_t 
     if (!aligned(coords, 4) || !aligned(out, 4))
         return fail(h, CLUSCO_ERR_INVALID_ARG, "coords and out must be 4-byte aligned");
     const int mode = mode_of(p);
-    const FwdLayout f = fwd_layout(mode, N, L);
-    if (!ws || ws_bytes < f.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    const SingleLayout s = single_layout(h, mode, N, L);
+    if (!ws || ws_bytes < s.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
     if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
-    hipStream_t s = (hipStream_t)stream;
-    char *w = (char *)ws;
-    int *counter = (int *)(w + f.off_counter);
-    double *E = (double *)(w + f.off_E);
-    double *cen = (double *)(w + f.off_cen);
-
-    PrepArgs pa{coords, N, L, f.Np, f.Lp, f.KB, w + f.off_ops, E, cen, counter};
-    hipError_t e = launch_prep(mode, pa, s);
-    if (e != hipSuccess) return hip_fail(h, e, "prep launch");
-
-    const double coef = flag_coef(h, mode, L);
-    if (mode != MODE_FP64) {
-        TileArgs ta{};
-        ta.ops = w + f.off_ops;
-        ta.E = E;
-        ta.N = N;
-        ta.L = L;
-        ta.Np = f.Np;
-        ta.KB = f.KB;
-        ta.nb = f.Np / TILE;
-        ta.T = tri_count(ta.nb);
-        ta.out = out;
-        ta.flag_coef = coef;
-        ta.counter = counter;
-        ta.list = (uint32_t *)(w + f.off_list);
-        e = launch_tile(mode, ta, s);
-        if (e != hipSuccess) return hip_fail(h, e, "tile launch");
-        if (coef > 0.0) {
-            FixupArgs fa{coords, cen, E, N, L, f.nrb, out, coef, counter,
-                         (const uint32_t *)(w + f.off_list), 0};
-            e = launch_fixup(fa, s);
-            if (e != hipSuccess) return hip_fail(h, e, "fixup launch");
-        }
-    } else {
-        FixupArgs fa{coords, cen, E, N, L, f.nrb, out, 0.0, nullptr, nullptr, f.n_wave_tiles};
-        e = launch_fixup(fa, s);
-        if (e != hipSuccess) return hip_fail(h, e, "fp64 launch");
-    }
-    return CLUSCO_OK;
+    return enqueue(h, mode, coords, coords, (char *)ws, out, &s, nullptr, TK_SYM,
+                   (hipStream_t)stream, true);
 }
 
 clusco_status clusco_fixup_count(clusco_handle h, const void *ws, int64_t *count, void *stream)
@@ -203,6 +564,251 @@ clusco_status clusco_fixup_count(clusco_handle h, const void *ws, int64_t *count
     if (e != hipSuccess) return hip_fail(h, e, "read fix-up counter");
     *count = v;
     return CLUSCO_OK;
+}
+
+clusco_status clusco_stage_timing(clusco_handle h, int max_calls)
+{
+    if (!h || max_calls < 0) return CLUSCO_ERR_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+    h->slots = h->used = 0;
+    for (int k = 0; k < 4 * max_calls; ++k) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return hip_fail(h, err, "create timing events");
+        h->events.push_back(e);
+    }
+    h->slots = max_calls;
+    return CLUSCO_OK;
+}
+
+clusco_status clusco_stage_times(clusco_handle h, double ms[3], int *calls)
+{
+    if (!h || !ms || !calls) return CLUSCO_ERR_INVALID_ARG;
+    ms[0] = ms[1] = ms[2] = 0.0;
+    *calls = h->used;
+    if (h->used == 0) return CLUSCO_OK;
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    hipError_t err = hipEventSynchronize(h->events[4 * h->used - 1]);
+    if (err != hipSuccess) return hip_fail(h, err, "wait for timing events");
+    for (int c = 0; c < h->used; ++c) {
+        for (int k = 0; k < 3; ++k) {
+            float t = 0.0f;
+            err = hipEventElapsedTime(&t, h->events[4 * c + k], h->events[4 * c + k + 1]);
+            if (err != hipSuccess) return hip_fail(h, err, "read timing events");
+            ms[k] += t;
+        }
+    }
+    h->used = 0;
+    return CLUSCO_OK;
+}
+
+// ------------------------------------------------------------- batched
+
+size_t clusco_crmsd_batched_workspace_size(clusco_handle h, int32_t E, const int64_t *h_N,
+                                           const int64_t *h_L, clusco_precision p)
+{
+    if (!h || !valid_precision(p)) return 0;
+    BatchInput b{E, h_N, h_L, nullptr, nullptr};
+    if (check_batch(h, b, false) != CLUSCO_OK) return 0;
+    return plan_layout(h, mode_of(p), b, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+clusco_status clusco_crmsd_batched(clusco_handle h, int32_t E, const int64_t *h_N,
+                                   const int64_t *h_L, const int64_t *h_coord_off,
+                                   const int64_t *h_out_off, const float *coords,
+                                   clusco_precision p, float *out, void *ws, size_t ws_bytes,
+                                   void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    BatchInput b{E, h_N, h_L, h_coord_off, h_out_off};
+    clusco_status st = check_batch(h, b, true);
+    if (st != CLUSCO_OK || E == 0) return st;
+    bool work = false;
+    for (int32_t e = 0; e < E; ++e) work |= h_N[e] >= 2;
+    if (!work) return CLUSCO_OK;
+    if (!coords || !out) return fail(h, CLUSCO_ERR_INVALID_ARG, "null coords or out");
+    if (!aligned(coords, 4) || !aligned(out, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "coords and out must be 4-byte aligned");
+    const int mode = mode_of(p);
+    const size_t need =
+        plan_layout(h, mode, b, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (!ws || ws_bytes < need) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    BatchPlan *plan = nullptr;
+    st = get_plan(h, mode, b, &plan);
+    if (st != CLUSCO_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+
+    // Direct launches while stage timing records or while the caller is
+    // itself capturing a graph; otherwise replay (or capture) the plan's graph.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return hip_fail(h, e, "query stream capture");
+    const bool timing = h->used < h->slots;
+    if (timing || cs != hipStreamCaptureStatusNone)
+        return enqueue(h, mode, coords, coords, (char *)ws, out, nullptr, plan, TK_BATCH, s,
+                       timing);
+
+    if (!plan->exec || plan->g_coords != coords || plan->g_out != out || plan->g_ws != ws) {
+        if (plan->exec) {
+            (void)hipGraphExecDestroy(plan->exec);
+            plan->exec = nullptr;
+        }
+        if (!h->capture) {
+            e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(h, e, "create capture stream");
+        }
+        e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(h, e, "begin capture");
+        st = enqueue(h, mode, coords, coords, (char *)ws, out, nullptr, plan, TK_BATCH,
+                     h->capture, false);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(h->capture, &graph);
+        if (st != CLUSCO_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "end capture");
+        e = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            plan->exec = nullptr;
+            return hip_fail(h, e, "instantiate graph");
+        }
+        plan->g_coords = coords;
+        plan->g_out = out;
+        plan->g_ws = ws;
+    }
+    e = hipGraphLaunch(plan->exec, s);
+    if (e != hipSuccess) return hip_fail(h, e, "graph launch");
+    return CLUSCO_OK;
+}
+
+// ------------------------------------------------------------------ cross
+
+size_t clusco_crmsd_cross_workspace_size(clusco_handle h, int64_t Na, int64_t Nb, int64_t L,
+                                         clusco_precision p)
+{
+    if (!h || Na < 0 || Nb < 0 || Na > MAX_N || Nb > MAX_N || L < 1 || !valid_precision(p))
+        return 0;
+    return cross_layout(h, mode_of(p), Na, Nb, L).total;
+}
+
+clusco_status clusco_crmsd_cross(clusco_handle h, const float *A, int64_t Na, const float *B,
+                                 int64_t Nb, int64_t L, clusco_precision p, float *out,
+                                 void *ws, size_t ws_bytes, void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (Na < 0 || Nb < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need Na, Nb >= 0, L >= 1");
+    if (Na > MAX_N || Nb > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "set above 2^20 models");
+    if (Na == 0 || Nb == 0) return CLUSCO_OK;
+    if (!A || !B || !out) return fail(h, CLUSCO_ERR_INVALID_ARG, "null A, B or out");
+    if (!aligned(A, 4) || !aligned(B, 4) || !aligned(out, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "A, B and out must be 4-byte aligned");
+    const int mode = mode_of(p);
+    const SingleLayout s = cross_layout(h, mode, Na, Nb, L);
+    if (!ws || ws_bytes < s.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    return enqueue(h, mode, A, B, (char *)ws, out, &s, nullptr, TK_RECT, (hipStream_t)stream,
+                   true);
+}
+
+// --------------------------------------------------------------- backward
+
+size_t clusco_crmsd_backward_workspace_size(clusco_handle h, int64_t N, int64_t L,
+                                            clusco_precision p)
+{
+    if (!h || N < 0 || N > MAX_N || L < 1 || !valid_precision(p)) return 0;
+    return bwd_layout(h, mode_of(p), N, N, L, false).total;
+}
+
+clusco_status clusco_crmsd_backward(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                    const float *rmsd, const float *grad_out,
+                                    clusco_precision p, float *grad_coords, void *ws,
+                                    size_t ws_bytes, void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (N < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0 and L >= 1");
+    if (N > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
+    if (N == 0) return CLUSCO_OK;
+    if (!grad_coords || !aligned(grad_coords, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "grad_coords null or misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (N == 1) {
+        DeviceGuard g(h->device);
+        if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+        hipError_t e = launch_zero(grad_coords, 3 * L, s);
+        return e == hipSuccess ? CLUSCO_OK : hip_fail(h, e, "zero launch");
+    }
+    if (!coords || !rmsd || !grad_out)
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "null coords, rmsd or grad_out");
+    if (!aligned(coords, 4) || !aligned(rmsd, 4) || !aligned(grad_out, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "inputs must be 4-byte aligned");
+    const int mode = mode_of(p);
+    const BwdLayout b = bwd_layout(h, mode, N, N, L, false);
+    if (!ws || ws_bytes < b.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    return enqueue_bwd(h, mode, coords, coords, (char *)ws, b, false, rmsd, grad_out, grad_coords,
+                       nullptr, s);
+}
+
+size_t clusco_crmsd_cross_backward_workspace_size(clusco_handle h, int64_t Na, int64_t Nb,
+                                                  int64_t L, clusco_precision p)
+{
+    if (!h || Na < 0 || Nb < 0 || Na > MAX_N || Nb > MAX_N || L < 1 || !valid_precision(p))
+        return 0;
+    return bwd_layout(h, mode_of(p), Na, Nb, L, true).total;
+}
+
+clusco_status clusco_crmsd_cross_backward(clusco_handle h, const float *A, int64_t Na,
+                                          const float *B, int64_t Nb, int64_t L,
+                                          const float *rmsd, const float *grad_out,
+                                          clusco_precision p, float *grad_A, float *grad_B,
+                                          void *ws, size_t ws_bytes, void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (Na < 0 || Nb < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need Na, Nb >= 0, L >= 1");
+    if (Na > MAX_N || Nb > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "set above 2^20 models");
+    if ((Na > 0 && !grad_A) || !aligned(grad_A, 4) || !aligned(grad_B, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "grad_A null or gradients misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (Na == 0 || Nb == 0) {
+        DeviceGuard g(h->device);
+        if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+        hipError_t e = launch_zero(grad_A, 3 * L * Na, s);
+        if (e == hipSuccess && grad_B) e = launch_zero(grad_B, 3 * L * Nb, s);
+        return e == hipSuccess ? CLUSCO_OK : hip_fail(h, e, "zero launch");
+    }
+    if (!A || !B || !rmsd || !grad_out)
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "null A, B, rmsd or grad_out");
+    if (!aligned(A, 4) || !aligned(B, 4) || !aligned(rmsd, 4) || !aligned(grad_out, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "inputs must be 4-byte aligned");
+    const int mode = mode_of(p);
+    const BwdLayout b = bwd_layout(h, mode, Na, Nb, L, true);
+    if (!ws || ws_bytes < b.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    return enqueue_bwd(h, mode, A, B, (char *)ws, b, true, rmsd, grad_out, grad_A, grad_B, s);
 }
 
 } // extern "C"

@@ -7,19 +7,18 @@
 // stored scores of each listed block, compacts the flagged pairs in LDS and
 // recomputes each one from the raw float32 coordinates entirely in FP64
 // (centring with the FP64 centroids, H and both radii accumulated in FP64,
-// then the same Eq. 2 epilogue).  With no list (FP64 precision) every pair of
-// every block is computed this way.
+// then the same Eq. 2 epilogue).  With `all` set (FP64 precision) every pair
+// of every block is computed this way.
 #include "eq2.h"
 #include "internal.h"
 
 namespace clusco {
 
-__device__ __forceinline__ float pair_fp64(const float *X, const double *cen, int64_t L,
-                                           int64_t i, int64_t j)
+__device__ __forceinline__ float pair_fp64(const float *xi, const float *xj, const double *ci,
+                                           const double *cj, int64_t L)
 {
-    const float *xi = X + i * L * 3, *xj = X + j * L * 3;
-    const double ci0 = cen[3 * i], ci1 = cen[3 * i + 1], ci2 = cen[3 * i + 2];
-    const double cj0 = cen[3 * j], cj1 = cen[3 * j + 1], cj2 = cen[3 * j + 2];
+    const double ci0 = ci[0], ci1 = ci[1], ci2 = ci[2];
+    const double cj0 = cj[0], cj1 = cj[1], cj2 = cj[2];
     double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double ea = 0.0, eb = 0.0;
     for (int64_t l = 0; l < L; ++l) {
@@ -37,47 +36,70 @@ __device__ __forceinline__ float pair_fp64(const float *X, const double *cen, in
     return (float)sqrt(fmax(lr2 / (double)L, 0.0));
 }
 
-__global__ __launch_bounds__(64) void fixup_kernel(FixupArgs a)
+__global__ __launch_bounds__(64) void fixup_kernel(FixupLaunch a)
 {
     __shared__ uint16_t todo[ROWBLK * ROWBLK];
     __shared__ int cnt;
     const int lane = threadIdx.x;
-    const int64_t N = a.N;
-    const int64_t n = a.counter ? (int64_t)*a.counter : a.n_all;
+    const int64_t n = a.all ? a.n_all : (int64_t)a.counters[0];
     for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        int e = 0;
         int64_t Ra, Rb;
-        if (a.counter) {
-            const uint32_t v = a.list[t];
-            Ra = v >> 16;
-            Rb = v & 0xFFFFu;
+        if (a.all) {
+            if (a.table) e = table_find(a.table, a.nprob, t, [](const Problem &q) { return q.wtile0; });
         } else {
-            tri_decode(t, a.nrb, &Ra, &Rb);
+            e = (int)a.list[t].prob;
         }
+        const Problem &p = a.table ? a.table[e] : a.prob;
+        if (a.all) {
+            const int64_t u = t - p.wtile0;
+            if (p.sym) {
+                tri_decode(u, p.nrbA, &Ra, &Rb);
+            } else {
+                Ra = u / p.nrbB;
+                Rb = u - Ra * p.nrbB;
+            }
+        } else {
+            const uint32_t b = a.list[t].blk;
+            Ra = b >> 16;
+            Rb = b & 0xFFFFu;
+        }
+        const int64_t NA = p.NA, NB = p.NB, L = p.L;
+        const double *EA = (const double *)(a.ws + p.EA);
+        const double *EB = (const double *)(a.ws + p.EB);
+        float *out = a.out + p.out;
         if (lane == 0) cnt = 0;
         __syncthreads();
-        for (int p = lane; p < ROWBLK * ROWBLK; p += 64) {
-            const int64_t i = Ra * ROWBLK + (p >> 5), j = Rb * ROWBLK + (p & 31);
-            if (i < j && j < N) {
+        for (int q = lane; q < ROWBLK * ROWBLK; q += 64) {
+            const int64_t i = Ra * ROWBLK + (q >> 5), j = Rb * ROWBLK + (q & 31);
+            const bool live = p.sym ? (i < j && j < NA) : (i < NA && j < NB);
+            if (live) {
                 bool need = true;
-                if (a.counter)
-                    need = (double)a.out[packed_index(i, j, N)] < a.flag_coef * (a.E[i] + a.E[j]);
-                if (need) todo[atomicAdd(&cnt, 1)] = (uint16_t)p;
+                if (!a.all) {
+                    const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
+                    need = (double)out[k] < p.flag_coef * (EA[i] + EB[j]);
+                }
+                if (need) todo[atomicAdd(&cnt, 1)] = (uint16_t)q;
             }
         }
         __syncthreads();
         const int m = cnt;
+        const float *XA = a.XA + p.XA, *XB = a.XB + p.XB;
+        const double *cenA = (const double *)(a.ws + p.cenA);
+        const double *cenB = (const double *)(a.ws + p.cenB);
         for (int s = lane; s < m; s += 64) {
-            const int p = todo[s];
-            const int64_t i = Ra * ROWBLK + (p >> 5), j = Rb * ROWBLK + (p & 31);
-            a.out[packed_index(i, j, N)] = pair_fp64(a.X, a.cen, a.L, i, j);
+            const int q = todo[s];
+            const int64_t i = Ra * ROWBLK + (q >> 5), j = Rb * ROWBLK + (q & 31);
+            const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
+            out[k] = pair_fp64(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j, L);
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_fixup(const FixupArgs &a, hipStream_t s)
+hipError_t launch_fixup(const FixupLaunch &a, hipStream_t s)
 {
-    int64_t grid = a.counter ? 2048 : (a.n_all < 65536 ? a.n_all : 65536);
+    int64_t grid = a.all ? (a.n_all < 65536 ? a.n_all : 65536) : 2048;
     if (grid < 1) grid = 1;
     fixup_kernel<<<dim3((unsigned)grid), dim3(64), 0, s>>>(a);
     return hipGetLastError();

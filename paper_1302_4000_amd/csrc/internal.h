@@ -45,8 +45,8 @@ __host__ __device__ inline int64_t packed_index(int64_t i, int64_t j, int64_t N)
     return i * (2 * N - i - 1) / 2 + (j - i - 1);
 }
 
-// Row of the upper triangle (diagonal included) that holds linear tile t,
-// for an nb x nb grid of tiles in row-major order.
+// (row, column) of linear index t in the row-major upper triangle (diagonal
+// included) of an nb x nb grid.
 __host__ __device__ inline void tri_decode(int64_t t, int64_t nb, int64_t *bi, int64_t *bj)
 {
     double B = 2.0 * (double)nb + 1.0;
@@ -62,77 +62,193 @@ __host__ __device__ inline void tri_decode(int64_t t, int64_t nb, int64_t *bi, i
 
 __host__ __device__ inline int64_t tri_count(int64_t nb) { return nb * (nb + 1) / 2; }
 
-// Workspace of one forward call (byte offsets, all 256-aligned).
-struct FwdLayout {
-    int mode;
-    int64_t N, L, Np, Lp, KB;
-    int64_t nrb;          // row blocks of 32
-    int64_t n_wave_tiles; // 32x32 blocks in the upper triangle (diagonal included)
-    size_t off_counter, off_E, off_cen, off_ops, off_list, total;
-};
-
-inline FwdLayout fwd_layout(int mode, int64_t N, int64_t L)
+// Banded order over the upper triangle of an nb x nb tile grid, for L2 reuse:
+// bands of G tile rows, each swept column by column (rows inside a column),
+// so consecutive tiles share a column of B and a band's rows of A stay
+// resident.  A band first covers its own diagonal G x G triangle (column c
+// holds rows 0..c), then every later column with all G rows.  Bijective onto
+// {(bi, bj): 0 <= bi <= bj < nb}.
+__host__ __device__ inline void band_decode(int64_t t, int64_t nb, int64_t G, int64_t *bi,
+                                            int64_t *bj)
 {
-    FwdLayout f{};
-    f.mode = mode;
-    f.N = N;
-    f.L = L;
-    f.Np = round_up(N > 0 ? N : 1, TILE);
-    f.Lp = round_up(L, kblock(mode));
-    f.KB = f.Lp / kblock(mode);
-    f.nrb = f.Np / ROWBLK;
-    f.n_wave_tiles = tri_count(f.nrb);
-    size_t o = 0;
-    auto take = [&](size_t bytes) { size_t r = o; o += (size_t)round_up((int64_t)bytes, 256); return r; };
-    f.off_counter = take(256);
-    f.off_E = take(sizeof(double) * f.Np);
-    f.off_cen = take(sizeof(double) * 3 * f.Np);
-    size_t op_bytes = 0;
-    if (mode == MODE_FP32) op_bytes = sizeof(float) * 3 * f.Np * f.Lp;
-    else if (mode == MODE_BF16 || mode == MODE_FP16) op_bytes = 2 * 2 * 3 * f.Np * f.Lp;
-    f.off_ops = take(op_bytes);
-    f.off_list = take(sizeof(uint32_t) * f.n_wave_tiles);
-    f.total = o;
-    return f;
+    int64_t r0 = 0;
+    for (;;) {
+        const int64_t g = nb - r0 < G ? nb - r0 : G;          // rows in this band
+        const int64_t n = g * (g + 1) / 2 + g * (nb - r0 - g);
+        if (t < n || r0 + g >= nb) {
+            const int64_t d = g * (g + 1) / 2;
+            if (t < d) {
+                int64_t c = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+                while (c * (c + 1) / 2 > t) --c;
+                while ((c + 1) * (c + 2) / 2 <= t) ++c;
+                *bi = r0 + (t - c * (c + 1) / 2);
+                *bj = r0 + c;
+            } else {
+                const int64_t u = t - d;
+                *bi = r0 + u % g;
+                *bj = r0 + g + u / g;
+            }
+            return;
+        }
+        t -= n;
+        r0 += g;
+    }
 }
 
-// ----------------------------------------------------- launch interfaces
+// Banded order over a full na x nb tile grid (bands of G rows, column-major).
+__host__ __device__ inline void band_decode_rect(int64_t t, int64_t na, int64_t nb, int64_t G,
+                                                 int64_t *bi, int64_t *bj)
+{
+    const int64_t band = t / (G * nb);
+    const int64_t r0 = band * G;
+    const int64_t g = na - r0 < G ? na - r0 : G;
+    const int64_t u = t - band * G * nb;
+    *bi = r0 + u % g;
+    *bj = u / g;
+}
 
-struct PrepArgs {
-    const float *X;    // [N][L][3]
-    int64_t N, L, Np, Lp, KB;
-    void *ops;         // operand chunks (null in FP64 mode)
-    double *E;         // [Np] sum_i |a_i|^2 of the operand values
-    double *cen;       // [Np][3] centroids (FP64)
-    int *counter;      // zeroed here (fix-up list length)
+__host__ inline size_t op_bytes_per_model(int mode, int64_t Lp)
+{
+    if (mode == MODE_FP32) return sizeof(float) * 3 * Lp;
+    if (mode == MODE_BF16 || mode == MODE_FP16) return 2 * 2 * 3 * Lp;
+    return 0;
+}
+
+// ------------------------------------------------------------ problems
+//
+// A model set is a run of models of one length whose operands the prep pass
+// writes.  A problem is one all-vs-all ensemble (A == B, packed output) or
+// one cross comparison of two sets (dense Na x Nb output).  All offsets are
+// relative to the bases passed at launch (coordinate arrays, workspace,
+// output), so a table of sets or problems does not depend on the buffers.
+
+struct ModelSet {
+    int64_t X;            // float offset of the set's first coordinate
+    int64_t N, Np, L, Lp, KB;
+    int64_t model0;       // prefix of padded models over the launch
+    int64_t ops;          // byte offset of the operand chunks in the workspace
+    int64_t E;            // byte offset of the radii (double [Np])
+    int64_t cen;          // byte offset of the centroids (double [Np][3])
+    int32_t use_b;        // coordinates come from the second base pointer
+    int32_t pad;
 };
 
-struct TileArgs {
-    const void *ops;
-    const double *E;
-    int64_t N, L, Np, KB;
-    int64_t nb;        // 64-model tile rows
-    int64_t T;         // tiles in the triangle
-    float *out;        // packed
-    double flag_coef;  // a pair is flagged when score < flag_coef * (E_i + E_j); <= 0: never
-    int *counter;
-    uint32_t *list;
+struct Problem {
+    int64_t NA, NB, L, KB;
+    int64_t nbA, nbB;     // 64-model tiles per side
+    int64_t nrbA, nrbB;   // 32-model row blocks per side
+    int64_t tile0;        // first 64x64 tile of this problem in the launch
+    int64_t wtile0;       // first 32x32 block of this problem in the launch
+    int64_t opsA, opsB, EA, EB, cenA, cenB;   // workspace byte offsets
+    int64_t XA, XB;       // float offsets into the first / second coordinate base
+    int64_t out;          // float offset into the output base
+    double flag_coef;     // flag a pair when score < flag_coef (E_i + E_j); <= 0 never
+    int32_t sym;          // 1: all-vs-all (packed, i < j); 0: dense NA x NB
+    int32_t pad;
 };
 
-struct FixupArgs {
-    const float *X;      // raw coordinates [N][L][3]
-    const double *cen;   // [Np][3]
-    const double *E;     // operand radii (flag re-evaluation only)
-    int64_t N, L, nrb;
+__host__ __device__ inline int64_t problem_tiles(const Problem &p)
+{
+    return p.sym ? tri_count(p.nbA) : p.nbA * p.nbB;
+}
+
+__host__ __device__ inline int64_t problem_wtiles(const Problem &p)
+{
+    return p.sym ? tri_count(p.nrbA) : p.nrbA * p.nrbB;
+}
+
+// Fix-up list entry: problem index and the 32x32 block (row, column blocks).
+struct FixEntry {
+    uint32_t prob;
+    uint32_t blk;         // (Ra << 16) | Rb
+};
+
+// Kernel launch descriptors.  Single problems travel inline; batched launches
+// pass a device table (sorted by the host) plus its length.
+struct PrepLaunch {
+    const float *XA, *XB;
+    char *ws;
+    ModelSet set[2];      // inline sets (single / cross launches)
+    const ModelSet *table;
+    int32_t nset;
+    int32_t mode;
+    int64_t total;        // padded models over all sets
+    int *counters;        // [0] fix-up list length, [1] work counter (zeroed here)
+};
+
+struct TileLaunch {
+    char *ws;
     float *out;
-    double flag_coef;
-    const int *counter;  // list length (null: every 32x32 block of the triangle)
-    const uint32_t *list;
-    int64_t n_all;       // number of 32x32 blocks when counter is null
+    Problem prob;         // inline problem (single / cross launches)
+    const Problem *table; // batched launches (prob unused)
+    int32_t nprob;
+    int32_t kind;         // TK_SYM, TK_RECT, TK_BATCH
+    int64_t T;            // 64x64 tiles in the launch
+    int *counters;
+    FixEntry *list;
+    // backward pass only: forward scores, incoming gradients, and the per-pair
+    // record [w Q (9), w, 0, 0] written at 12 floats per output index
+    const float *rmsd, *gout;
+    float *wq;
 };
 
-hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t s);
-hipError_t launch_tile(int mode, const TileArgs &a, hipStream_t s);
-hipError_t launch_fixup(const FixupArgs &a, hipStream_t s);
+enum TileKind { TK_SYM = 0, TK_RECT = 1, TK_BATCH = 2 };
+enum TileOp { OP_FWD = 0, OP_BWD = 1 };
+
+// Gradient pass: for every model m of the row set, over all partners j,
+//   grad_m = (sum_j w_mj) a_m - sum_j Q~_mj a_j
+// with Q~ = Q of the record, or its transpose when m is the second model of
+// the pair.
+struct GradLaunch {
+    const float *XR, *XC;     // raw coordinates of rows / partners
+    const double *cenR, *cenC;
+    const float *wq;          // per-pair records
+    float *grad;              // [NR][L][3]
+    int64_t NR, NC, L;
+    int32_t kind;             // GK_SYM, GK_CROSS_A, GK_CROSS_B
+    int32_t pad;
+};
+
+enum GradKind { GK_SYM = 0, GK_CROSS_A = 1, GK_CROSS_B = 2 };
+
+struct FixupLaunch {
+    const float *XA, *XB;
+    const char *ws;
+    float *out;
+    Problem prob;
+    const Problem *table;
+    int32_t nprob;
+    int32_t all;          // 1: recompute every pair of every block (FP64 precision)
+    int64_t n_all;        // 32x32 blocks in the launch when all = 1
+    const int *counters;
+    const FixEntry *list;
+};
+
+// Workspace of one launch: counters, then per-set regions, then the list.
+struct WsLayout {
+    size_t total;
+    size_t off_counters;  // 256 bytes
+    size_t off_list;      // FixEntry [max_blocks]
+    int64_t max_blocks;
+};
+
+hipError_t launch_prep(const PrepLaunch &a, hipStream_t s);
+hipError_t launch_tile(int mode, const TileLaunch &a, hipStream_t s, int op = OP_FWD);
+hipError_t launch_grad(const GradLaunch &a, hipStream_t s);
+hipError_t launch_zero(float *p, int64_t n, hipStream_t s);
+hipError_t launch_fixup(const FixupLaunch &a, hipStream_t s);
+
+// Device-side lookup of the entry of a prefix-sorted table holding index t.
+template <typename T, typename F>
+__device__ __forceinline__ int table_find(const T *tab, int n, int64_t t, F start)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start(tab[mid]) <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 } // namespace clusco

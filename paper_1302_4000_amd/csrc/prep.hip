@@ -2,8 +2,8 @@
 // fragment-native layout described in internal.h, and record each model's
 // sum of squared centred coordinates (E = L R^2, Eq. 2) computed from exactly
 // the operand values the contraction will use, plus its FP64 centroid for
-// the fix-up.  One wave per model; HBM-bound (reads 12 L bytes, writes the
-// operands once).
+// the fix-up.  One wave per (padded) model over all model sets of a launch;
+// HBM-bound (reads 12 L bytes per model, writes the operands once).
 #include "internal.h"
 
 namespace clusco {
@@ -29,14 +29,24 @@ __device__ __forceinline__ float bf16_bits_to_float(uint16_t b)
 }
 
 template <int MODE>
-__global__ __launch_bounds__(64) void prep_kernel(PrepArgs a)
+__global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 {
-    const int64_t m = blockIdx.x;
+    const int64_t g = blockIdx.x;
     const int lane = threadIdx.x;
-    if (m == 0 && lane == 0) *a.counter = 0;
-    const int64_t L = a.L;
-    const bool real = m < a.N;
-    const float *x = a.X + (real ? m : 0) * L * 3;
+    if (g == 0 && lane < 2) a.counters[lane] = 0;
+
+    ModelSet s;
+    if (a.table) {
+        s = a.table[table_find(a.table, a.nset, g, [](const ModelSet &m) { return m.model0; })];
+    } else {
+        s = (a.nset > 1 && g >= a.set[1].model0) ? a.set[1] : a.set[0];
+    }
+    const int64_t m = g - s.model0;
+    const int64_t L = s.L;
+    const bool real = m < s.N;
+    const float *x = (s.use_b ? a.XB : a.XA) + s.X + (real ? m : 0) * L * 3;
+    double *E = (double *)(a.ws + s.E);
+    double *cen = (double *)(a.ws + s.cen);
 
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
     if (real) {
@@ -51,20 +61,21 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepArgs a)
         c2 = wave_sum(c2) * inv;
     }
     if (lane == 0) {
-        a.cen[3 * m] = c0;
-        a.cen[3 * m + 1] = c1;
-        a.cen[3 * m + 2] = c2;
+        cen[3 * m] = c0;
+        cen[3 * m + 1] = c1;
+        cen[3 * m + 2] = c2;
     }
     if (MODE == MODE_FP64) {
-        if (lane == 0) a.E[m] = 0.0;
+        if (lane == 0) E[m] = 0.0;
         return;
     }
 
     const int64_t R = m / ROWBLK;
     const int r = (int)(m % ROWBLK);
+    const int64_t KB = s.KB;
     const double cc[3] = {c0, c1, c2};
     double e = 0.0;
-    for (int64_t l = lane; l < a.Lp; l += 64) {
+    for (int64_t l = lane; l < s.Lp; l += 64) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double v = (real && l < L) ? (double)x[3 * l + c] - cc[c] : 0.0;
@@ -72,14 +83,14 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepArgs a)
                 const float f = (float)v;
                 e += (double)f * (double)f;
                 const int64_t kb = l >> 3, h = (l >> 2) & 1, el = l & 3;
-                const int64_t idx = (((R * a.KB + kb) * 3 + c) * 64 + r + 32 * h) * 4 + el;
-                ((float *)a.ops)[idx] = f;
+                const int64_t idx = (((R * KB + kb) * 3 + c) * 64 + r + 32 * h) * 4 + el;
+                ((float *)(a.ws + s.ops))[idx] = f;
             } else {
                 const int64_t kb = l >> 4, h = (l >> 3) & 1, el = l & 7;
-                const int64_t base = (((R * a.KB + kb) * 3 + c) * 2) * 64;
+                const int64_t base = (((R * KB + kb) * 3 + c) * 2) * 64;
                 const int64_t hi_idx = (base + r + 32 * h) * 8 + el;
                 const int64_t lo_idx = (base + 64 + r + 32 * h) * 8 + el;
-                uint16_t *ops = (uint16_t *)a.ops;
+                uint16_t *ops = (uint16_t *)(a.ws + s.ops);
                 double hv, lv;
                 if (MODE == MODE_BF16) {
                     const uint16_t hb = bf16_bits_rn((float)v);
@@ -96,19 +107,19 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepArgs a)
                     ops[hi_idx] = __builtin_bit_cast(uint16_t, hh);
                     ops[lo_idx] = __builtin_bit_cast(uint16_t, ll);
                 }
-                const double s = hv + lv;   // exact in FP64
-                e += s * s;
+                const double sv = hv + lv;   // exact in FP64
+                e += sv * sv;
             }
         }
     }
     e = wave_sum(e);
-    if (lane == 0) a.E[m] = e;
+    if (lane == 0) E[m] = e;
 }
 
-hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t s)
+hipError_t launch_prep(const PrepLaunch &a, hipStream_t s)
 {
-    dim3 grid((unsigned)a.Np), block(64);
-    switch (mode) {
+    dim3 grid((unsigned)a.total), block(64);
+    switch (a.mode) {
     case MODE_FP32: prep_kernel<MODE_FP32><<<grid, block, 0, s>>>(a); break;
     case MODE_BF16: prep_kernel<MODE_BF16><<<grid, block, 0, s>>>(a); break;
     case MODE_FP16: prep_kernel<MODE_FP16><<<grid, block, 0, s>>>(a); break;

@@ -1,18 +1,21 @@
-// Fused covariance contraction + Eq. 2 epilogue + packed store.
+// Fused covariance contraction + Eq. 2 epilogue + coalesced store.
 //
 // The nine correlations H_cd[i][j] = sum_l X_c[i][l] X_d[j][l] of every pair
-// of models (c, d in {x, y, z}) are the blocks of the symmetric product
-// Y Y^T, Y = the centred coordinate planes.  One workgroup owns a 64x64 tile
-// of model pairs in the upper triangle (tile rows <= tile columns); each of
-// its four waves owns a 32x32 sub-tile and keeps nine MFMA accumulator sets,
-// one per (c, d), so all nine entries of a pair's H sit in the same lane and
-// register slot.  After the K loop each lane runs the FP64 Eq. 2 epilogue on
-// its 16 pairs and stores them; for a fixed register slot the 64 lanes write
-// two 128-byte runs of the packed row (consecutive j), so stores coalesce.
+// of models (c, d in {x, y, z}) are the blocks of the product Y_A Y_B^T,
+// Y = the centred coordinate planes.  One workgroup owns a 64x64 tile of
+// model pairs; each of its four waves owns a 32x32 sub-tile and keeps nine
+// MFMA accumulator sets, one per (c, d), so all nine entries of a pair's H
+// sit in the same lane and register slot.  After the K loop each lane runs
+// the FP64 Eq. 2 epilogue on its 16 pairs and stores them; for a fixed
+// register slot the 64 lanes write two 128-byte runs of consecutive j, so
+// stores coalesce in both the packed and the dense output.
 //
-// Blocks are remapped so that each XCD (workgroups are dealt round-robin to
-// the 8 XCDs) receives a contiguous range of tiles, which share operand rows
-// in that XCD's L2.
+// Launch kinds:
+//  TK_SYM    one all-vs-all ensemble; tiles of the upper triangle only (the
+//            wave below the diagonal of a diagonal tile idles);
+//  TK_RECT   one cross comparison, every tile of the NA x NB grid;
+//  TK_BATCH  many all-vs-all ensembles in one launch.
+// The kernel is persistent with a ping-pong schedule; see tile_kernel.
 #include "eq2.h"
 #include "internal.h"
 
@@ -23,6 +26,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Keeps the compiler from sinking the next K-block's loads down to their
+// first use, which would expose the full L2 latency on every K-block.
+__device__ __forceinline__ void pin_order() { asm volatile("" ::: "memory"); }
 
 template <int MODE>
 __device__ __forceinline__ f32x16 mfma_split(u32x4 a, u32x4 b, f32x16 c)
@@ -37,28 +44,29 @@ __device__ __forceinline__ f32x16 mfma_split(u32x4 a, u32x4 b, f32x16 c)
 
 // Contraction of one 32x32 wave tile: acc[3c+d] += X_c[Ra rows] X_d[Rb rows]^T
 template <int MODE>
-__device__ __forceinline__ void contract(const void *ops, int64_t Ra, int64_t Rb, int64_t KB,
-                                         int lane, f32x16 acc[9])
+__device__ __forceinline__ void contract(const char *opsA, const char *opsB, int64_t Ra,
+                                         int64_t Rb, int64_t KB, int lane, f32x16 acc[9])
 {
     if constexpr (MODE == MODE_FP32) {
-        const f32x4 *pa = (const f32x4 *)ops + Ra * KB * 3 * 64 + lane;
-        const f32x4 *pb = (const f32x4 *)ops + Rb * KB * 3 * 64 + lane;
+        const f32x4 *pa = (const f32x4 *)opsA + Ra * KB * 3 * 64 + lane;
+        const f32x4 *pb = (const f32x4 *)opsB + Rb * KB * 3 * 64 + lane;
         f32x4 A[3], B[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             A[c] = pa[c * 64];
             B[c] = pb[c * 64];
         }
+        // the next K-block is always fetched (the last step re-reads its own
+        // block) so the loop body has no branches
         for (int64_t kb = 0; kb < KB; ++kb) {
+            const int64_t nx = (kb + 1 < KB ? kb + 1 : kb) * 3 * 64;
             f32x4 An[3], Bn[3];
-            const bool more = kb + 1 < KB;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                if (more) {
-                    An[c] = pa[((kb + 1) * 3 + c) * 64];
-                    Bn[c] = pb[((kb + 1) * 3 + c) * 64];
-                }
+                An[c] = pa[nx + c * 64];
+                Bn[c] = pb[nx + c * 64];
             }
+            pin_order();
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -67,122 +75,308 @@ __device__ __forceinline__ void contract(const void *ops, int64_t Ra, int64_t Rb
                     for (int d = 0; d < 3; ++d)
                         acc[3 * c + d] = __builtin_amdgcn_mfma_f32_32x32x2f32(
                             A[c][e], B[d][e], acc[3 * c + d], 0, 0, 0);
-            if (more) {
+            pin_order();
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    A[c] = An[c];
-                    B[c] = Bn[c];
-                }
+            for (int c = 0; c < 3; ++c) {
+                A[c] = An[c];
+                B[c] = Bn[c];
             }
         }
     } else {
-        // chunk (kb, c, part) of row block R at ((R*KB + kb)*3 + c)*2 + part
-        const u32x4 *pa = (const u32x4 *)ops + Ra * KB * 6 * 64 + lane;
-        const u32x4 *pb = (const u32x4 *)ops + Rb * KB * 6 * 64 + lane;
-        u32x4 A[6], B[6];
+        // chunk (kb, c, part) of row block R at ((R*KB + kb)*3 + c)*2 + part.
+        // Only the hi parts are prefetched a whole K-block ahead; each lo part
+        // is reloaded as soon as the last MFMA group reading it has issued,
+        // which keeps the wave within 256 registers (two waves per SIMD).  The
+        // last step re-reads its own block so the loop body has no branches.
+        const u32x4 *pa = (const u32x4 *)opsA + Ra * KB * 6 * 64 + lane;
+        const u32x4 *pb = (const u32x4 *)opsB + Rb * KB * 6 * 64 + lane;
+        u32x4 Ah[3], Al[3], Bh[3], Bl[3];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            A[q] = pa[q * 64];
-            B[q] = pb[q * 64];
+        for (int c = 0; c < 3; ++c) {
+            Ah[c] = pa[(2 * c) * 64];
+            Al[c] = pa[(2 * c + 1) * 64];
+            Bh[c] = pb[(2 * c) * 64];
+            Bl[c] = pb[(2 * c + 1) * 64];
         }
         for (int64_t kb = 0; kb < KB; ++kb) {
-            u32x4 An[6], Bn[6];
-            const bool more = kb + 1 < KB;
+            const int64_t nx = (kb + 1 < KB ? kb + 1 : kb) * 6 * 64;
+            u32x4 Ahn[3], Bhn[3];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                if (more) {
-                    An[q] = pa[((kb + 1) * 6 + q) * 64];
-                    Bn[q] = pb[((kb + 1) * 6 + q) * 64];
-                }
+            for (int c = 0; c < 3; ++c) {
+                Ahn[c] = pa[nx + (2 * c) * 64];
+                Bhn[c] = pb[nx + (2 * c) * 64];
             }
+            pin_order();
             // hi*hi', then hi*lo', then lo*hi': each accumulator is touched
             // once per group of nine, so back-to-back MFMAs are independent
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    acc[3 * c + d] = mfma_split<MODE>(A[2 * c], B[2 * d], acc[3 * c + d]);
+                    acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bh[d], acc[3 * c + d]);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    acc[3 * c + d] = mfma_split<MODE>(A[2 * c], B[2 * d + 1], acc[3 * c + d]);
+                    acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
+            pin_order();
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Bl[d] = pb[nx + (2 * d + 1) * 64];
+            pin_order();
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    acc[3 * c + d] = mfma_split<MODE>(A[2 * c + 1], B[2 * d], acc[3 * c + d]);
-            if (more) {
+                    acc[3 * c + d] = mfma_split<MODE>(Al[c], Bh[d], acc[3 * c + d]);
+            pin_order();
 #pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    A[q] = An[q];
-                    B[q] = Bn[q];
-                }
+            for (int c = 0; c < 3; ++c) {
+                Al[c] = pa[nx + (2 * c + 1) * 64];
+                Ah[c] = Ahn[c];
+                Bh[c] = Bhn[c];
             }
+            pin_order();
         }
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void tile_kernel(TileArgs a)
+// Tile rows per band of the launch order: 8 x 8 tiles in flight per XCD touch
+// about 2 MB of operands, well inside its 4 MB L2.
+constexpr int64_t BAND = 8;
+
+// A wave's share of one 64x64 tile: its 32x32 block and the problem.
+struct WaveJob {
+    int64_t Ra, Rb;
+    int32_t pidx;
+    int32_t active;
+};
+
+template <int KIND>
+__device__ __forceinline__ const Problem &problem_of(const TileLaunch &a, int32_t pidx)
+{
+    if constexpr (KIND == TK_BATCH) return a.table[pidx];
+    else return a.prob;
+}
+
+// Wave w's quarter of launch tile t (inactive past the end, below the
+// diagonal of a diagonal tile, or entirely in padding).
+template <int KIND>
+__device__ __forceinline__ WaveJob decode_job(const TileLaunch &a, int64_t t, int w)
+{
+    WaveJob job{0, 0, 0, 0};
+    if (t >= a.T) return job;
+    int64_t bi, bj;
+    int32_t e = 0;
+    if constexpr (KIND == TK_BATCH) {
+        e = table_find(a.table, a.nprob, t, [](const Problem &q) { return q.tile0; });
+        tri_decode(t - a.table[e].tile0, a.table[e].nbA, &bi, &bj);
+    } else if constexpr (KIND == TK_SYM) {
+        band_decode(t, a.prob.nbA, BAND, &bi, &bj);
+    } else {
+        band_decode_rect(t, a.prob.nbA, a.prob.nbB, BAND, &bi, &bj);
+    }
+    const Problem &p = problem_of<KIND>(a, e);
+    const int wy = w >> 1, wx = w & 1;
+    job.Ra = 2 * bi + wy;
+    job.Rb = 2 * bj + wx;
+    job.pidx = e;
+    job.active = !(p.sym && bi == bj && wy > wx) && job.Ra * ROWBLK < p.NA &&
+                 job.Rb * ROWBLK < p.NB;
+    return job;
+}
+
+// FP64 Eq. 2 epilogue and store of one wave's 32x32 block.  The lane holds
+// column j = lane%32 and rows 8(r/4) + 4(lane/32) + r%4 of accumulator slot r.
+// Every slot is evaluated (padding rows and columns have H = 0 and E = 0,
+// which is finite); only the store and the flag are predicated, so the FP64
+// work runs without divergent branches.
+__device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
+                                         const WaveJob &job, int lane, const f32x16 acc[9])
+{
+    const int64_t NA = p.NA, NB = p.NB;
+    const double *EA = (const double *)(a.ws + p.EA);
+    const double *EB = (const double *)(a.ws + p.EB);
+    float *out = a.out + p.out;
+    const double invL = 1.0 / (double)p.L;
+    const double coef = p.flag_coef;
+    const int64_t j = job.Rb * ROWBLK + (lane & 31);
+    const double Ej = EB[j];
+    const bool jlive = j < (p.sym ? NA : NB);
+    bool flagged = false;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int64_t i0 = job.Ra * ROWBLK + 8 * g + 4 * (lane >> 5);
+        // row base k(i, j) - j: packed rows advance by N - i - 2, dense by NB
+        int64_t base = p.sym ? i0 * (2 * NA - i0 - 1) / 2 - i0 - 1 : i0 * NB;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * g + q;
+            const int64_t i = i0 + q;
+            double h[9];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) h[u] = (double)acc[u][r];
+            const double Ei = EA[i];
+            const double lr2 = eq2_lrmsd2(h, Ei, Ej);
+            const float v = sqrtf((float)fmax(lr2 * invL, 0.0));
+            const bool live = jlive && (p.sym ? i < j : i < NA);
+            if (live) out[base + j] = v;
+            flagged |= live && (double)v < coef * (Ei + Ej);
+            base += p.sym ? NA - i - 2 : NB;
+        }
+    }
+    if (__any(flagged) && lane == 0) {
+        const int s = atomicAdd(&a.counters[0], 1);
+        a.list[s] = FixEntry{(uint32_t)job.pidx, ((uint32_t)job.Ra << 16) | (uint32_t)job.Rb};
+    }
+}
+
+// Backward epilogue: per live pair, w = g / (L cRMSD) (0 where the score
+// is 0 to within 1e-5 of the pair's mean radius, where cRMSD is not
+// differentiable) and the adjoint Q of the pair's H; writes [w Q, w, 0, 0].
+__device__ __forceinline__ void bwd_epilogue(const TileLaunch &a, const Problem &p,
+                                             const WaveJob &job, int lane, const f32x16 acc[9])
+{
+    const int64_t NA = p.NA, NB = p.NB;
+    const double *EA = (const double *)(a.ws + p.EA);
+    const double *EB = (const double *)(a.ws + p.EB);
+    const double L = (double)p.L;
+    const int64_t j = job.Rb * ROWBLK + (lane & 31);
+    const double Ej = EB[j];
+    const bool jlive = j < (p.sym ? NA : NB);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int64_t i0 = job.Ra * ROWBLK + 8 * g + 4 * (lane >> 5);
+        int64_t base = p.sym ? i0 * (2 * NA - i0 - 1) / 2 - i0 - 1 : i0 * NB;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * g + q;
+            const int64_t i = i0 + q;
+            const bool live = jlive && (p.sym ? i < j : i < NA);
+            if (live) {
+                const int64_t k = base + j;
+                const double sc = (double)a.rmsd[k], gk = (double)a.gout[k];
+                const double floor_r = 1e-5 * sqrt((EA[i] + Ej) / (2.0 * L));
+                const double w = (gk != 0.0 && sc > floor_r) ? gk / (L * sc) : 0.0;
+                float rec[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                if (w != 0.0) {
+                    double h[9], qm[9];
+#pragma unroll
+                    for (int u = 0; u < 9; ++u) h[u] = (double)acc[u][r];
+                    eq2_adjoint(h, qm);
+#pragma unroll
+                    for (int u = 0; u < 9; ++u) rec[u] = (float)(w * qm[u]);
+                    rec[9] = (float)w;
+                }
+                f32x4 *dst = (f32x4 *)(a.wq + 12 * k);
+                dst[0] = f32x4{rec[0], rec[1], rec[2], rec[3]};
+                dst[1] = f32x4{rec[4], rec[5], rec[6], rec[7]};
+                dst[2] = f32x4{rec[8], rec[9], rec[10], rec[11]};
+            }
+            base += p.sym ? NA - i - 2 : NB;
+        }
+    }
+}
+
+// Persistent ping-pong kernel.  A workgroup is two groups of four waves, one
+// wave of each group per SIMD.  At phase ph the group of parity ph runs the
+// MFMA contraction of the workgroup's tile ph while the other group runs the
+// FP64 epilogue of tile ph-1 (which it contracted in the previous phase), so
+// the matrix cores and the FP64 VALUs of every SIMD work at the same time.
+// One barrier per phase keeps the groups in step; the tile index of each
+// phase goes through a three-slot LDS ring, so a slot is never rewritten
+// while a wave of the previous phase may still read it.
+//
+// Tile order: TK_SYM / TK_RECT follow the banded order, split into eight
+// contiguous chunks, one per XCD (workgroups are dealt round-robin to the
+// XCDs), whose workgroups take the chunk's tiles round-robin, one per phase.
+// TK_BATCH takes tiles from a global counter in the host's order (most
+// expensive tiles first), so uneven ensembles balance.
+template <int MODE, int KIND, int OP>
+__global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
 {
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int64_t per_xcd = gridDim.x >> 3;
-    const int64_t t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (t >= a.T) return;
-    int64_t bi, bj;
-    tri_decode(t, a.nb, &bi, &bj);
-    const int wy = w >> 1, wx = w & 1;
-    if (bi == bj && wy > wx) return;           // sub-tile entirely below the diagonal
-    const int64_t Ra = 2 * bi + wy, Rb = 2 * bj + wx;
-    const int64_t N = a.N;
-    if (Ra * ROWBLK >= N || Rb * ROWBLK >= N) return;   // padding only
+    const int wave = threadIdx.x >> 6;
+    const int grp = wave >> 2;
+    const int w = wave & 3;
+    __shared__ int64_t s_tile[3];
+    const int64_t per = gridDim.x >> 3;
+    const int64_t xcd = blockIdx.x & 7, jw = blockIdx.x >> 3;
+    const int64_t c0 = a.T * xcd / 8, c1 = a.T * (xcd + 1) / 8;
 
     f32x16 acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-
-    contract<MODE>(a.ops, Ra, Rb, a.KB, lane, acc);
-
-    // epilogue: lane holds column j = lane%32 and rows 8(r/4) + 4(lane/32) + r%4
-    const double invL = 1.0 / (double)a.L;
-    const int64_t j = Rb * ROWBLK + (lane & 31);
-    const double Ej = a.E[j];
-    bool flagged = false;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int64_t i = Ra * ROWBLK + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (i < j && j < N) {
-            double h[9];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) h[q] = (double)acc[q][r];
-            const double Ei = a.E[i];
-            const double lr2 = eq2_lrmsd2(h, Ei, Ej);
-            const float v = sqrtf((float)fmax(lr2 * invL, 0.0));
-            a.out[packed_index(i, j, N)] = v;
-            flagged |= (double)v < a.flag_coef * (Ei + Ej);
+    WaveJob job{0, 0, 0, 0};
+    for (int64_t ph = 0;; ++ph) {
+        if (threadIdx.x == 0) {
+            int64_t t;
+            if constexpr (KIND == TK_BATCH) {
+                t = atomicAdd(&a.counters[1], 1);
+            } else {
+                t = c0 + jw + per * ph;
+                if (t >= c1) t = a.T;
+            }
+            s_tile[ph % 3] = t;
         }
-    }
-    if (__any(flagged) && lane == 0) {
-        const int s = atomicAdd(a.counter, 1);
-        a.list[s] = ((uint32_t)Ra << 16) | (uint32_t)Rb;
+        __syncthreads();
+        const int64_t tk = s_tile[ph % 3];
+        const int64_t te = ph > 0 ? s_tile[(ph + 2) % 3] : a.T;
+        if (tk >= a.T && te >= a.T) break;
+        if ((int)(ph & 1) == grp) {
+            job = decode_job<KIND>(a, tk, w);
+            if (job.active) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+                const Problem &p = problem_of<KIND>(a, job.pidx);
+                contract<MODE>(a.ws + p.opsA, a.ws + p.opsB, job.Ra, job.Rb, p.KB, lane, acc);
+            }
+        } else if (job.active) {
+            if constexpr (OP == OP_FWD) epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
+            else bwd_epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
+            job.active = 0;
+        }
     }
 }
 
-hipError_t launch_tile(int mode, const TileArgs &a, hipStream_t s)
+template <int MODE>
+static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, int op)
 {
-    const int64_t grid = round_up(a.T, 8);
-    dim3 g((unsigned)grid), b(256);
-    switch (mode) {
-    case MODE_FP32: tile_kernel<MODE_FP32><<<g, b, 0, s>>>(a); break;
-    case MODE_BF16: tile_kernel<MODE_BF16><<<g, b, 0, s>>>(a); break;
-    case MODE_FP16: tile_kernel<MODE_FP16><<<g, b, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
+    dim3 g((unsigned)grid), b(512);
+    if (op == OP_BWD) {
+        if (a.kind == TK_SYM) tile_kernel<MODE, TK_SYM, OP_BWD><<<g, b, 0, s>>>(a);
+        else if (a.kind == TK_RECT) tile_kernel<MODE, TK_RECT, OP_BWD><<<g, b, 0, s>>>(a);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    switch (a.kind) {
+    case TK_SYM: tile_kernel<MODE, TK_SYM, OP_FWD><<<g, b, 0, s>>>(a); break;
+    case TK_RECT: tile_kernel<MODE, TK_RECT, OP_FWD><<<g, b, 0, s>>>(a); break;
+    default: tile_kernel<MODE, TK_BATCH, OP_FWD><<<g, b, 0, s>>>(a); break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_tile(int mode, const TileLaunch &a, hipStream_t s, int op)
+{
+    // persistent: one workgroup (8 waves) per CU, a multiple of 8 so every
+    // XCD gets the same number of workgroups; every workgroup leaves its
+    // phase loop once both of its groups have run out of tiles
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t grid = round_up(cus, 8);
+    const int64_t need = round_up(a.T > 0 ? a.T : 1, 8);
+    if (grid > need) grid = need;
+    switch (mode) {
+    case MODE_FP32: return launch_mode<MODE_FP32>(a, s, grid, op);
+    case MODE_BF16: return launch_mode<MODE_BF16>(a, s, grid, op);
+    case MODE_FP16: return launch_mode<MODE_FP16>(a, s, grid, op);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 } // namespace clusco

@@ -1,0 +1,108 @@
+"""GPU parity of the many-vs-reference (cross) and batched entry points
+against the FP64 oracle, and consistency with the single-ensemble path."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_4000_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "fp64": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def cl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1302_4000_amd as m
+    for p, t in TOL.items():
+        m.set_tolerance(p, t)
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp64"])
+@pytest.mark.parametrize("Na,Nb,L", [(70, 45, 33), (130, 1, 100), (1, 66, 17), (65, 64, 150)])
+def test_cross_matches_oracle(cl, prec, Na, Nb, L):
+    say(f"[cross] Na={Na} Nb={Nb} L={L} {prec}")
+    x = synth.make_ensemble(77 + L, Na + Nb, L, sigma=(0.3, 4.0))
+    A, B = x[:Na], x[Na:]
+    want = oracle.crmsd_cross(A, B)
+    got = cl.crmsd_cross(dev(A), dev(B), prec).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    assert got.shape == want.shape
+    assert np.abs(got - want).max() < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_target_vs_many_n4096_l256(cl, prec):
+    say(f"[cross] target-vs-many N=4096 L=256 {prec}")
+    x, native = synth.grad_workload()
+    got = cl.crmsd_cross(dev(x), dev(native[None]), prec).cpu().numpy()[:, 0].astype(np.float64)
+    want = oracle.crmsd_cross(x, native[None])[:, 0]
+    assert np.abs(got - want).max() < TOL[prec]
+
+
+def test_cross_of_a_set_with_itself_matches_matrix(cl):
+    say("[cross] self-cross vs packed matrix")
+    x = synth.make_ensemble(5, 90, 40)
+    C = cl.crmsd_cross(dev(x), dev(x), "fp32").cpu().numpy()
+    m = cl.crmsd_matrix(dev(x), "fp32").cpu().numpy()
+    I, J = np.triu_indices(90, 1)
+    assert np.abs(C[I, J] - m).max() < 2e-4
+    assert np.abs(np.diag(C)).max() < 1e-3
+
+
+def small_batch():
+    ens = synth.make_batch(E=16, scale_n=0.06)
+    ens += [synth.make_ensemble(9, 1, 30), synth.make_ensemble(10, 2, 1),
+            synth.make_ensemble(11, 33, 7), synth.make_ensemble(12, 0, 12)]
+    return ens
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp64"])
+def test_batched_matches_oracle_and_single_calls(cl, prec):
+    ens = small_batch()
+    say(f"[batched] {len(ens)} ensembles {[e.shape[:2] for e in ens]} {prec}")
+    b = cl.Batch([e.shape[:2] for e in ens])
+    flat = b.pack([torch.from_numpy(e) for e in ens], "cuda")
+    out = cl.crmsd_batched(b, flat, prec)
+    parts = b.split(out)
+    for e, part in zip(ens, parts):
+        if e.shape[0] < 2:
+            assert part.numel() == 0
+            continue
+        got = part.cpu().numpy().astype(np.float64)
+        want = oracle.crmsd_matrix(e)
+        assert np.abs(got - want).max() < TOL[prec], e.shape
+        single = cl.crmsd_matrix(dev(e), prec).cpu()
+        assert torch.equal(single, part.cpu()), e.shape
+
+
+def test_batched_graph_replay_is_stable(cl):
+    say("[batched] graph replays")
+    ens = synth.make_batch(E=8, scale_n=0.05)
+    b = cl.Batch([e.shape[:2] for e in ens])
+    flat = b.pack([torch.from_numpy(e) for e in ens], "cuda")
+    ws = torch.empty(cl.batched_workspace_size(b, "bf16"), dtype=torch.uint8, device="cuda")
+    out = torch.empty(b.n_out, dtype=torch.float32, device="cuda")
+    ref = cl.crmsd_batched(b, flat, "bf16", out=out.clone(), ws=ws).clone()
+    for rep in range(4):
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        cl.crmsd_batched(b, flat, "bf16", out=out, ws=ws)   # replays the cached graph
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+    # new buffers: the graph is re-captured
+    out2 = cl.crmsd_batched(b, flat.clone(), "bf16")
+    torch.cuda.synchronize()
+    assert torch.equal(out2, ref)

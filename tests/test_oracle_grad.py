@@ -99,3 +99,12 @@ def test_cross_gradient_is_sum_of_pair_gradients(orc):
             wA[i] += g[i, j] * a
             wB[j] += g[i, j] * b
     assert np.abs(gA - wA).max() < 1e-12 and np.abs(gB - wB).max() < 1e-12
+
+
+def test_matrix_gradient_rows_match_full(orc):
+    x = synth.make_ensemble(25, 9, 12, sigma=(0.5, 3.0)).astype(np.float64)
+    N = len(x)
+    g = np.random.default_rng(2).normal(size=N * (N - 1) // 2)
+    full = orc.crmsd_matrix_grad(x, g)
+    rows = np.array([0, 4, 8, 4])
+    assert np.abs(orc.crmsd_matrix_grad_rows(x, g, rows) - full[rows]).max() < 1e-12
