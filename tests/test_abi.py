@@ -102,3 +102,68 @@ def test_binding_refuses_cpu_tensors():
     from paper_1302_4000_amd import crmsd_matrix
     with pytest.raises(TypeError):
         crmsd_matrix(torch.zeros(4, 5, 3))
+
+
+def test_cross_argument_errors(L, h):
+    f = L.clusco_crmsd_cross
+    need = L.clusco_crmsd_cross_workspace_size(h, 50, 1, 30, 0)
+    assert need > 0
+    assert f(h, FAKE, 50, FAKE, 1, 0, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, -1, FAKE, 1, 30, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, None, 50, FAKE, 1, 30, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 50, None, 1, 30, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 50, FAKE, 1, 30, 0, FAKE, FAKE, need - 1, None) == binding.ERR_WORKSPACE
+    assert f(h, FAKE, 50, FAKE, 1, 30, 5, FAKE, FAKE, need, None) == binding.ERR_UNSUPPORTED
+    assert f(h, None, 0, None, 7, 30, 0, None, None, 0, None) == binding.OK
+    assert f(h, None, 7, None, 0, 30, 0, None, None, 0, None) == binding.OK
+
+
+def _arr(vals):
+    a = (ctypes.c_int64 * len(vals))(*vals)
+    return a
+
+
+def test_batched_argument_errors_and_sizes(L, h):
+    N, Ls = _arr([100, 1, 300]), _arr([50, 20, 120])
+    co, oo = _arr([0, 15000, 15060]), _arr([0, 4950, 4950])
+    size = L.clusco_crmsd_batched_workspace_size(h, 3, N, Ls, 1)
+    # at least the two real ensembles' operands
+    assert size >= 2 * 2 * 3 * (128 * 64 + 320 * 128)
+    assert L.clusco_crmsd_batched_workspace_size(h, 3, None, Ls, 1) == 0
+    bad = _arr([100, -1, 300])
+    assert L.clusco_crmsd_batched_workspace_size(h, 3, bad, Ls, 1) == 0
+    f = L.clusco_crmsd_batched
+    assert f(h, -1, N, Ls, co, oo, FAKE, 1, FAKE, FAKE, size, None) == binding.ERR_INVALID_ARG
+    assert f(h, 3, N, Ls, None, oo, FAKE, 1, FAKE, FAKE, size, None) == binding.ERR_INVALID_ARG
+    assert f(h, 3, N, Ls, co, oo, None, 1, FAKE, FAKE, size, None) == binding.ERR_INVALID_ARG
+    assert f(h, 3, N, Ls, co, oo, FAKE, 1, FAKE, FAKE, size - 1, None) == binding.ERR_WORKSPACE
+    assert f(h, 3, N, Ls, _arr([0, -5, 0]), oo, FAKE, 1, FAKE, FAKE, size, None) == \
+        binding.ERR_INVALID_ARG
+    assert f(h, 3, N, Ls, co, oo, FAKE, 9, FAKE, FAKE, size, None) == binding.ERR_UNSUPPORTED
+    # nothing to compute: E = 0, or every ensemble below two models
+    assert f(h, 0, None, None, None, None, None, 1, None, None, 0, None) == binding.OK
+    ones = _arr([1, 0])
+    assert f(h, 2, ones, _arr([5, 5]), _arr([0, 15]), _arr([0, 0]), None, 1, None, None, 0,
+             None) == binding.OK
+
+
+def test_backward_argument_errors(L, h):
+    f = L.clusco_crmsd_backward
+    need = L.clusco_crmsd_backward_workspace_size(h, 64, 40, 0)
+    assert need > L.clusco_crmsd_workspace_size(h, 64, 40, 0)
+    assert need >= 12 * 4 * 64 * 63 // 2
+    assert f(h, FAKE, 64, 0, FAKE, FAKE, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 64, 40, None, FAKE, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 64, 40, FAKE, FAKE, 0, None, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 64, 40, FAKE, FAKE, 0, FAKE, FAKE, need - 1, None) == binding.ERR_WORKSPACE
+    assert f(h, FAKE, 64, 40, FAKE, FAKE, 8, FAKE, FAKE, need, None) == binding.ERR_UNSUPPORTED
+    assert f(h, None, 0, 40, None, None, 0, None, None, 0, None) == binding.OK
+    g = L.clusco_crmsd_cross_backward
+    needc = L.clusco_crmsd_cross_backward_workspace_size(h, 64, 1, 40, 1)
+    assert needc > 0
+    assert g(h, FAKE, 64, FAKE, 1, 40, FAKE, FAKE, 1, None, FAKE, FAKE, needc, None) == \
+        binding.ERR_INVALID_ARG
+    assert g(h, FAKE, 64, FAKE, 1, 40, FAKE, FAKE, 1, FAKE, FAKE, FAKE, needc - 1, None) == \
+        binding.ERR_WORKSPACE
+    assert g(h, None, 64, FAKE, 1, 40, FAKE, FAKE, 1, FAKE, FAKE, FAKE, needc, None) == \
+        binding.ERR_INVALID_ARG
