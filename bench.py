@@ -147,6 +147,79 @@ def oracle_leg(x_np, outs, want_cpu, threads):
     return errs, cpu
 
 
+def timed(torch, fn, steps, warmup):
+    """Mean wall ms of fn() over `steps` calls after `warmup`, synchronised."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def batched_leg(cl, torch, steps):
+    """64 uneven ensembles (N ~ logU[100,2000], L ~ logU[50,500]) in one
+    launch sequence, replayed from the cached graph."""
+    from paper_1302_4000_amd import synth
+    ens = synth.make_batch()
+    b = cl.Batch([e.shape[:2] for e in ens])
+    flat = b.pack([torch.from_numpy(e) for e in ens], "cuda")
+    res = {"ensembles": len(ens), "pairs": b.n_out,
+           "models": int(sum(e.shape[0] for e in ens))}
+    for prec in ("bf16", "fp32"):
+        ws = torch.empty(cl.batched_workspace_size(b, prec), dtype=torch.uint8, device="cuda")
+        out = torch.empty(b.n_out, dtype=torch.float32, device="cuda")
+        ms = timed(torch, lambda: cl.crmsd_batched(b, flat, prec, out=out, ws=ws), steps, 2)
+        res[prec] = {"ms_per_call": ms, "pairs_per_s": b.n_out / (ms * 1e-3)}
+    return res
+
+
+def backward_leg(cl, torch, steps):
+    """Forward + hand-written backward of the mean pairwise cRMSD over the
+    N=4096, L=256 ensemble, and of the mean cRMSD of every model against the
+    native (target-vs-many)."""
+    from paper_1302_4000_amd import synth
+    x_np, native = synth.grad_workload()
+    N, L = x_np.shape[0], x_np.shape[1]
+    P = N * (N - 1) // 2
+    x = torch.from_numpy(x_np).cuda()
+    ref = torch.from_numpy(native[None]).cuda()
+    g = torch.full((P,), 1.0 / P, device="cuda")
+    gt = torch.full((N, 1), 1.0 / N, device="cuda")
+    res = {"workload": "n4096_l256", "N": N, "L": L, "pairs": P}
+    for prec in ("fp32", "bf16"):
+        out = cl.crmsd_matrix(x, prec)
+        fwd = timed(torch, lambda: cl.crmsd_matrix(x, prec, out=out), steps, 1)
+        bwd = timed(torch, lambda: cl.crmsd_backward(x, out, g, prec), steps, 1)
+        tv = cl.crmsd_cross(x, ref, prec)
+        tfwd = timed(torch, lambda: cl.crmsd_cross(x, ref, prec, out=tv), steps, 1)
+        tbwd = timed(torch, lambda: cl.crmsd_cross_backward(x, ref, tv, gt, prec), steps, 1)
+        res[prec] = {"forward_ms": fwd, "backward_ms": bwd,
+                     "fwd_bwd_pairs_per_s": P / ((fwd + bwd) * 1e-3),
+                     "target_vs_many_forward_ms": tfwd, "target_vs_many_backward_ms": tbwd}
+    return res
+
+
+def threshold_leg(cl, torch, x, steps):
+    """Pairs below 3.2 A (the paper's threshold example) on the same
+    ensemble, emitted without storing the packed matrix."""
+    N = x.shape[0]
+    P = N * (N - 1) // 2
+    res = {"cutoff_A": 3.2}
+    for prec in ("bf16",):
+        _, _, _, n = cl.crmsd_threshold(x, 3.2, prec)
+        cap = n + 1024
+        ws = torch.empty(cl.binding.lib().clusco_crmsd_threshold_workspace_size(
+            cl.binding.handle(x.device.index), N, x.shape[1], cl.PRECISION[prec]),
+            dtype=torch.uint8, device=x.device)
+        ms = timed(torch, lambda: cl.crmsd_threshold(x, 3.2, prec, capacity=cap, ws=ws,
+                                                      sync=False), steps, 1)
+        res[prec] = {"ms_per_call": ms, "pairs_per_s": P / (ms * 1e-3), "pairs_below": n}
+    return res
+
+
 def copy_calibration(nbytes: int):
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -169,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true", help="skip the oracle error sample")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-path comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and backward measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter scaling)")
     args = ap.parse_args()
@@ -212,6 +287,18 @@ def main():
                    algorithmic_tflops=18.0 * L * P / (cmp_res["tile_ms"] * 1e-3) / 1e12)
         outs["fp32"] = cmp_out
 
+    extra = {}
+    if not args.no_extra:
+        log("[bench] threshold 3.2 A")
+        extra["threshold"] = threshold_leg(cl, torch, x, max(3, args.steps // 2))
+        log(f"[bench] threshold: {extra['threshold']}")
+        log("[bench] batched: 64 uneven ensembles")
+        extra["batched"] = batched_leg(cl, torch, max(3, args.steps // 2))
+        log(f"[bench] batched: {extra['batched']}")
+        log("[bench] backward: N=4096 L=256")
+        extra["backward"] = backward_leg(cl, torch, max(3, args.steps // 2))
+        log(f"[bench] backward: {extra['backward']}")
+
     threads = max(1, min(16, os.cpu_count() or 1))
     errs, cpu = (None, None)
     if not (args.no_error and args.no_cpu_baseline):
@@ -246,6 +333,7 @@ def main():
         "max_err_A": errs,
         "fp32_path": cmp,
         "cpu_baseline": cpu,
+        **extra,
     }
     print(json.dumps(line), flush=True)
 

@@ -98,6 +98,23 @@ clusco_status clusco_crmsd_matrix(clusco_handle h, const float *coords, int64_t 
                                   clusco_precision p, float *out, void *ws, size_t ws_bytes,
                                   void *stream);
 
+/* Pairs within a cRMSD cutoff (Results and Discussion: selecting the pairs of
+ * models below a threshold, 3.2 A in the paper's example) without storing the
+ * N(N-1)/2 matrix.  Every pair (i, j), i < j, whose score (computed exactly as
+ * by clusco_crmsd_matrix, fix-up included) is below `cutoff` is appended to
+ * out_i / out_j / out_score (device int32, int32, float32 arrays of
+ * `capacity` entries) in no particular order.  *count (device uint64,
+ * 8-byte aligned) receives the number of such pairs; when it exceeds
+ * capacity only `capacity` of them are stored (call again with larger
+ * arrays).  Pairs whose score lies within the precision's tolerance of the
+ * cutoff may fall on either side. */
+size_t clusco_crmsd_threshold_workspace_size(clusco_handle h, int64_t N, int64_t L,
+                                             clusco_precision p);
+clusco_status clusco_crmsd_threshold(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                     clusco_precision p, float cutoff, int32_t *out_i,
+                                     int32_t *out_j, float *out_score, int64_t capacity,
+                                     uint64_t *count, void *ws, size_t ws_bytes, void *stream);
+
 /* Number of 32x32 pair blocks the last forward call on this workspace sent to
  * the FP64 fix-up.  Synchronises `stream`.  For diagnostics only. */
 clusco_status clusco_fixup_count(clusco_handle h, const void *ws, int64_t *count, void *stream);

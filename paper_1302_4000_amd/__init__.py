@@ -8,9 +8,11 @@ raises if it is not built.
 from .autograd import CRMSDCross, CRMSDMatrix, crmsd_cross_ad, crmsd_matrix_ad  # noqa: F401
 from .binding import (Batch, ClucsoError, PRECISION, batched_workspace_size,  # noqa: F401
                       crmsd_backward, crmsd_batched, crmsd_cross, crmsd_cross_backward,
-                      crmsd_matrix, fixup_count, set_tolerance, workspace_size)
+                      crmsd_matrix, crmsd_threshold, fixup_count, set_tolerance,
+                      workspace_size)
 
 __all__ = ["Batch", "CRMSDCross", "CRMSDMatrix", "ClucsoError", "PRECISION",
            "batched_workspace_size", "crmsd_backward", "crmsd_batched", "crmsd_cross",
            "crmsd_cross_ad", "crmsd_cross_backward", "crmsd_matrix", "crmsd_matrix_ad",
+           "crmsd_threshold",
            "fixup_count", "set_tolerance", "workspace_size"]

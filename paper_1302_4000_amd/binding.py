@@ -69,6 +69,9 @@ def lib():
             "clusco_crmsd_cross_backward_workspace_size": (sz, [vp, i64, i64, i64, st]),
             "clusco_crmsd_cross_backward": (st, [vp, vp, i64, vp, i64, i64, vp, vp, st, vp, vp,
                                                  vp, sz, vp]),
+            "clusco_crmsd_threshold_workspace_size": (sz, [vp, i64, i64, st]),
+            "clusco_crmsd_threshold": (st, [vp, vp, i64, i64, st, ctypes.c_float, vp, vp, vp, i64,
+                                            vp, vp, sz, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -326,3 +329,43 @@ def crmsd_cross_backward(a: torch.Tensor, b: torch.Tensor, rmsd: torch.Tensor,
                                            ws.numel(), _stream(dev))
     _check(rc, h, "clusco_crmsd_cross_backward")
     return ga, gb
+
+
+def crmsd_threshold(x: torch.Tensor, cutoff: float, precision="fp32",
+                    capacity: int | None = None, ws: torch.Tensor | None = None,
+                    sync: bool = True):
+    """Pairs (i, j), i < j, with cRMSD below `cutoff` (A), in no particular order.
+
+    Returns (i, j, score, count): int32, int32 and float32 device tensors of
+    min(count, capacity) entries and the number of such pairs.  With
+    capacity=None every pair is kept (a second call with exact arrays is made
+    when the first guess is too small).  With sync=False the arrays are
+    returned at full capacity with count as a device uint64 tensor.
+    """
+    x = _coords(x)
+    N, L = x.shape[0], x.shape[1]
+    dev = x.device
+    h = handle(dev.index)
+    p = _prec(precision)
+    P = N * (N - 1) // 2
+    need = int(lib().clusco_crmsd_threshold_workspace_size(h, N, L, p))
+    ws = _workspace(need, dev, ws)
+    auto = capacity is None
+    cap = min(P, 1 << 22) if auto else int(capacity)
+    for attempt in range(2):
+        oi = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        oj = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        os_ = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)   # holds the uint64 count
+        rc = lib().clusco_crmsd_threshold(h, _ptr(x), N, L, p, ctypes.c_float(cutoff), _ptr(oi),
+                                          _ptr(oj), _ptr(os_), cap, _ptr(cnt), _ptr(ws),
+                                          ws.numel(), _stream(dev))
+        _check(rc, h, "clusco_crmsd_threshold")
+        if not sync:
+            return oi, oj, os_, cnt
+        n = int(cnt.item())
+        if n <= cap or not auto:
+            k = min(n, cap)
+            return oi[:k], oj[:k], os_[:k], n
+        cap = n
+    raise RuntimeError("pair count changed between identical calls")

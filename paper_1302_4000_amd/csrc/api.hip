@@ -811,4 +811,121 @@ clusco_status clusco_crmsd_cross_backward(clusco_handle h, const float *A, int64
     return enqueue_bwd(h, mode, A, B, (char *)ws, b, true, rmsd, grad_out, grad_A, grad_B, s);
 }
 
+// -------------------------------------------------------------- threshold
+
+namespace {
+
+struct ThrLayout {
+    SingleLayout s;
+    size_t off_masks, total;
+};
+
+ThrLayout thr_layout(clusco_handle h, int mode, int64_t N, int64_t L)
+{
+    ThrLayout t{};
+    t.s = single_layout(h, mode, N, L);
+    size_t o = t.s.total;
+    t.off_masks = take(o, sizeof(uint32_t) * 32 * problem_wtiles(t.s.p));
+    t.total = o;
+    return t;
+}
+
+} // namespace
+
+size_t clusco_crmsd_threshold_workspace_size(clusco_handle h, int64_t N, int64_t L,
+                                             clusco_precision p)
+{
+    if (!h || N < 0 || N > MAX_N || L < 1 || !valid_precision(p)) return 0;
+    return thr_layout(h, mode_of(p), N, L).total;
+}
+
+clusco_status clusco_crmsd_threshold(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                     clusco_precision p, float cutoff, int32_t *out_i,
+                                     int32_t *out_j, float *out_score, int64_t capacity,
+                                     uint64_t *count, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (N < 0 || L < 1 || capacity < 0 || !(cutoff == cutoff))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0, L >= 1, capacity >= 0, cutoff not NaN");
+    if (N > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
+    if (!count || !aligned(count, 8)) return fail(h, CLUSCO_ERR_INVALID_ARG, "count null or misaligned");
+    hipStream_t st = (hipStream_t)stream;
+    if (N < 2) {
+        DeviceGuard g(h->device);
+        if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+        hipError_t e = launch_zero((float *)count, 2, st);
+        return e == hipSuccess ? CLUSCO_OK : hip_fail(h, e, "zero launch");
+    }
+    if (!coords || !aligned(coords, 4)) return fail(h, CLUSCO_ERR_INVALID_ARG, "coords null or misaligned");
+    if (capacity > 0 && (!out_i || !out_j || !out_score || !aligned(out_i, 4) ||
+                         !aligned(out_j, 4) || !aligned(out_score, 4)))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "output arrays null or misaligned");
+    const int mode = mode_of(p);
+    const ThrLayout t = thr_layout(h, mode, N, L);
+    if (!ws || ws_bytes < t.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    char *w = (char *)ws;
+    Emit em{};
+    em.cutoff = cutoff;
+    em.i = out_i;
+    em.j = out_j;
+    em.score = out_score;
+    em.capacity = capacity;
+    em.count = (unsigned long long *)count;
+    em.masks = (uint32_t *)(w + t.off_masks);
+
+    stage_mark(h, 0, st);
+    PrepLaunch pl{};
+    pl.XA = pl.XB = coords;
+    pl.ws = w;
+    pl.mode = mode;
+    pl.counters = (int *)w;
+    pl.zero64 = em.count;
+    pl.set[0] = pl.set[1] = t.s.A;
+    pl.nset = 1;
+    pl.total = t.s.A.Np;
+    hipError_t e = launch_prep(pl, st);
+    if (e != hipSuccess) return hip_fail(h, e, "prep launch");
+    stage_mark(h, 1, st);
+    FixupLaunch fl{};
+    fl.XA = fl.XB = coords;
+    fl.ws = w;
+    fl.prob = t.s.p;
+    fl.nprob = 1;
+    fl.counters = (int *)w;
+    fl.list = (const FixEntry *)(w + t.s.off_list);
+    fl.thr = 1;
+    fl.emit = em;
+    if (mode != MODE_FP64) {
+        TileLaunch tl{};
+        tl.ws = w;
+        tl.prob = t.s.p;
+        tl.nprob = 1;
+        tl.kind = TK_SYM;
+        tl.T = problem_tiles(t.s.p);
+        tl.counters = (int *)w;
+        tl.list = (FixEntry *)(w + t.s.off_list);
+        tl.emit = em;
+        e = launch_tile(mode, tl, st, OP_THR);
+        if (e != hipSuccess) return hip_fail(h, e, "threshold tile launch");
+        stage_mark(h, 2, st);
+        if (t.s.p.flag_coef > 0.0) {
+            e = launch_fixup(fl, st);
+            if (e != hipSuccess) return hip_fail(h, e, "fix-up launch");
+        }
+    } else {
+        stage_mark(h, 2, st);
+        fl.all = 1;
+        fl.n_all = problem_wtiles(t.s.p);
+        e = launch_fixup(fl, st);
+        if (e != hipSuccess) return hip_fail(h, e, "fp64 launch");
+    }
+    stage_mark(h, 3, st);
+    return CLUSCO_OK;
+}
+
 } // extern "C"

@@ -11,7 +11,10 @@
 // One workgroup owns GM models and one thread one atom: each partner's
 // centred coordinates are loaded once per workgroup and used for all GM
 // models; the per-pair records are wave-uniform and come in through scalar
-// loads.  Accumulation is FP32 in a fixed order (deterministic).
+// loads.  Accumulation is FP64 in a fixed order (deterministic): the two
+// terms nearly cancel when the partners surround the model (a reference
+// against many noisy copies of itself), and FP64 FMA costs what FP32 FMA
+// costs on this chip.
 #include "internal.h"
 
 namespace clusco {
@@ -23,17 +26,17 @@ __global__ __launch_bounds__(256) void grad_kernel(GradLaunch a)
     const int64_t m0 = (int64_t)blockIdx.x * GM;
     const int64_t NR = a.NR, NC = a.NC, L = a.L;
     for (int64_t l = threadIdx.x; l < L; l += blockDim.x) {
-        float acc[GM][3], wsum[GM];
+        double acc[GM][3], wsum[GM];
 #pragma unroll
         for (int mm = 0; mm < GM; ++mm) {
-            acc[mm][0] = acc[mm][1] = acc[mm][2] = 0.0f;
-            wsum[mm] = 0.0f;
+            acc[mm][0] = acc[mm][1] = acc[mm][2] = 0.0;
+            wsum[mm] = 0.0;
         }
         for (int64_t j = 0; j < NC; ++j) {
             const float *xj = a.XC + (j * L + l) * 3;
-            const float b0 = (float)((double)xj[0] - a.cenC[3 * j]);
-            const float b1 = (float)((double)xj[1] - a.cenC[3 * j + 1]);
-            const float b2 = (float)((double)xj[2] - a.cenC[3 * j + 2]);
+            const double b0 = (double)xj[0] - a.cenC[3 * j];
+            const double b1 = (double)xj[1] - a.cenC[3 * j + 1];
+            const double b2 = (double)xj[2] - a.cenC[3 * j + 2];
 #pragma unroll
             for (int mm = 0; mm < GM; ++mm) {
                 const int64_t m = m0 + mm;
@@ -51,15 +54,18 @@ __global__ __launch_bounds__(256) void grad_kernel(GradLaunch a)
                     k = j * NR + m;
                 }
                 const float *rk = a.wq + 12 * k;
-                wsum[mm] += rk[9];
+                double r[10];
+#pragma unroll
+                for (int u = 0; u < 10; ++u) r[u] = (double)rk[u];
+                wsum[mm] += r[9];
                 if (!tr) {
-                    acc[mm][0] += rk[0] * b0 + rk[1] * b1 + rk[2] * b2;
-                    acc[mm][1] += rk[3] * b0 + rk[4] * b1 + rk[5] * b2;
-                    acc[mm][2] += rk[6] * b0 + rk[7] * b1 + rk[8] * b2;
+                    acc[mm][0] += r[0] * b0 + r[1] * b1 + r[2] * b2;
+                    acc[mm][1] += r[3] * b0 + r[4] * b1 + r[5] * b2;
+                    acc[mm][2] += r[6] * b0 + r[7] * b1 + r[8] * b2;
                 } else {
-                    acc[mm][0] += rk[0] * b0 + rk[3] * b1 + rk[6] * b2;
-                    acc[mm][1] += rk[1] * b0 + rk[4] * b1 + rk[7] * b2;
-                    acc[mm][2] += rk[2] * b0 + rk[5] * b1 + rk[8] * b2;
+                    acc[mm][0] += r[0] * b0 + r[3] * b1 + r[6] * b2;
+                    acc[mm][1] += r[1] * b0 + r[4] * b1 + r[7] * b2;
+                    acc[mm][2] += r[2] * b0 + r[5] * b1 + r[8] * b2;
                 }
             }
         }
@@ -71,8 +77,8 @@ __global__ __launch_bounds__(256) void grad_kernel(GradLaunch a)
             float *gm = a.grad + (m * L + l) * 3;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float am = (float)((double)xm[c] - a.cenR[3 * m + c]);
-                gm[c] = wsum[mm] * am - acc[mm][c];
+                const double am = (double)xm[c] - a.cenR[3 * m + c];
+                gm[c] = (float)(wsum[mm] * am - acc[mm][c]);
             }
         }
     }

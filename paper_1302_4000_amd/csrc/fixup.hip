@@ -8,7 +8,9 @@
 // recomputes each one from the raw float32 coordinates entirely in FP64
 // (centring with the FP64 centroids, H and both radii accumulated in FP64,
 // then the same Eq. 2 epilogue).  With `all` set (FP64 precision) every pair
-// of every block is computed this way.
+// of every block is computed this way.  In threshold mode the candidates are
+// the pairs the tile kernel marked in the block's ownership mask, and the
+// recomputed pairs below the cutoff are appended to the output arrays.
 #include "eq2.h"
 #include "internal.h"
 
@@ -75,7 +77,11 @@ __global__ __launch_bounds__(64) void fixup_kernel(FixupLaunch a)
             const bool live = p.sym ? (i < j && j < NA) : (i < NA && j < NB);
             if (live) {
                 bool need = true;
-                if (!a.all) {
+                if (a.all) {
+                    need = true;
+                } else if (a.thr) {
+                    need = (a.emit.masks[32 * t + (q >> 5)] >> (q & 31)) & 1u;
+                } else {
                     const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
                     need = (double)out[k] < p.flag_coef * (EA[i] + EB[j]);
                 }
@@ -87,11 +93,36 @@ __global__ __launch_bounds__(64) void fixup_kernel(FixupLaunch a)
         const float *XA = a.XA + p.XA, *XB = a.XB + p.XB;
         const double *cenA = (const double *)(a.ws + p.cenA);
         const double *cenB = (const double *)(a.ws + p.cenB);
-        for (int s = lane; s < m; s += 64) {
-            const int q = todo[s];
-            const int64_t i = Ra * ROWBLK + (q >> 5), j = Rb * ROWBLK + (q & 31);
-            const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
-            out[k] = pair_fp64(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j, L);
+        for (int s0 = 0; s0 < m; s0 += 64) {   // uniform trip count (ballots below)
+            const int s = s0 + lane;
+            int64_t i = 0, j = 0;
+            float v = 0.0f;
+            if (s < m) {
+                const int q = todo[s];
+                i = Ra * ROWBLK + (q >> 5);
+                j = Rb * ROWBLK + (q & 31);
+                v = pair_fp64(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j, L);
+                if (!a.thr) out[p.sym ? packed_index(i, j, NA) : i * NB + j] = v;
+            }
+            if (a.thr) {
+                const bool em = s < m && v < (float)a.emit.cutoff;
+                const unsigned long long b = __ballot(em);
+                if (b) {
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(a.emit.count, (unsigned long long)__popcll(b));
+                    base = __shfl(base, 0, 64);
+                    if (em) {
+                        const unsigned long long pos =
+                            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                        if (pos < (unsigned long long)a.emit.capacity) {
+                            a.emit.i[pos] = (int32_t)i;
+                            a.emit.j[pos] = (int32_t)j;
+                            a.emit.score[pos] = v;
+                        }
+                    }
+                }
+            }
         }
         __syncthreads();
     }

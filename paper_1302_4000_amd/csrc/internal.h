@@ -174,6 +174,21 @@ struct PrepLaunch {
     int32_t mode;
     int64_t total;        // padded models over all sets
     int *counters;        // [0] fix-up list length, [1] work counter (zeroed here)
+    unsigned long long *zero64;   // zeroed here too when not null (emission count)
+};
+
+// Threshold emission: pairs (i, j), i < j, with score below `cutoff` are
+// appended (in no particular order) to three arrays of `capacity` entries;
+// *count receives how many there are (it may exceed capacity, in which case
+// only the first `capacity` appended are stored).  Pairs the FP64 fix-up
+// owns are marked in a per-block 32x32 bit mask instead and emitted there.
+struct Emit {
+    double cutoff;
+    int32_t *i, *j;
+    float *score;
+    int64_t capacity;
+    unsigned long long *count;
+    uint32_t *masks;      // [list entry][32 rows] fix-up ownership bits
 };
 
 struct TileLaunch {
@@ -190,10 +205,12 @@ struct TileLaunch {
     // record [w Q (9), w, 0, 0] written at 12 floats per output index
     const float *rmsd, *gout;
     float *wq;
+    Emit emit;            // threshold pass only
 };
 
 enum TileKind { TK_SYM = 0, TK_RECT = 1, TK_BATCH = 2 };
-enum TileOp { OP_FWD = 0, OP_BWD = 1 };
+enum TileOp { OP_FWD = 0, OP_BWD = 1, OP_THR = 2 };
+
 
 // Gradient pass: for every model m of the row set, over all partners j,
 //   grad_m = (sum_j w_mj) a_m - sum_j Q~_mj a_j
@@ -222,6 +239,9 @@ struct FixupLaunch {
     int64_t n_all;        // 32x32 blocks in the launch when all = 1
     const int *counters;
     const FixEntry *list;
+    int32_t thr;          // 1: emit pairs below emit.cutoff instead of storing scores
+    int32_t pad;
+    Emit emit;
 };
 
 // Workspace of one launch: counters, then per-set regions, then the list.

@@ -34,6 +34,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
     const int64_t g = blockIdx.x;
     const int lane = threadIdx.x;
     if (g == 0 && lane < 2) a.counters[lane] = 0;
+    if (g == 0 && lane == 0 && a.zero64) *a.zero64 = 0ull;
 
     ModelSet s;
     if (a.table) {

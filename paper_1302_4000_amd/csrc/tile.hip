@@ -277,6 +277,85 @@ __device__ __forceinline__ void bwd_epilogue(const TileLaunch &a, const Problem 
     }
 }
 
+// Number of lanes below this one whose bit is set in the wave-wide mask b.
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long b)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+}
+
+// Threshold epilogue: scores as in the forward epilogue, but instead of the
+// packed store, pairs below the cutoff are appended to the output arrays
+// (one atomic per wave for the whole 32x32 block, then each lane writes at
+// its prefix position).  Pairs the fix-up will recompute are not emitted
+// here; their bits go into the block's ownership mask with the list entry.
+__device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem &p,
+                                             const WaveJob &job, int lane, const f32x16 acc[9])
+{
+    const int64_t NA = p.NA;
+    const double *EA = (const double *)(a.ws + p.EA);
+    const double *EB = (const double *)(a.ws + p.EB);
+    const double invL = 1.0 / (double)p.L;
+    const double coef = p.flag_coef;
+    const float cutoff = (float)a.emit.cutoff;
+    const int64_t j = job.Rb * ROWBLK + (lane & 31);
+    const double Ej = EB[j];
+    const bool jlive = j < NA;
+    float vs[16];
+    uint32_t emit = 0, flag = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t i = job.Ra * ROWBLK + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        double h[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) h[u] = (double)acc[u][r];
+        const double Ei = EA[i];
+        const float v = sqrtf((float)fmax(eq2_lrmsd2(h, Ei, Ej) * invL, 0.0));
+        const bool live = jlive && i < j;
+        const bool fl = live && (double)v < coef * (Ei + Ej);
+        vs[r] = v;
+        flag |= (uint32_t)fl << r;
+        emit |= (uint32_t)(live && !fl && v < cutoff) << r;
+    }
+    if (__any(flag != 0)) {
+        int s = 0;
+        if (lane == 0) {
+            s = atomicAdd(&a.counters[0], 1);
+            a.list[s] = FixEntry{(uint32_t)job.pidx, ((uint32_t)job.Ra << 16) | (uint32_t)job.Rb};
+        }
+        s = __shfl(s, 0, 64);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const unsigned long long b = __ballot((flag >> r) & 1u);
+            const int row = 8 * (r >> 2) + (r & 3);
+            if (lane == 0) {
+                a.emit.masks[32 * s + row] = (uint32_t)b;
+                a.emit.masks[32 * s + row + 4] = (uint32_t)(b >> 32);
+            }
+        }
+    }
+    uint32_t total = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) total += (uint32_t)__popcll(__ballot((emit >> r) & 1u));
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.emit.count, (unsigned long long)total);
+    base = __shfl(base, 0, 64);
+    unsigned long long off = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const unsigned long long b = __ballot((emit >> r) & 1u);
+        if ((emit >> r) & 1u) {
+            const unsigned long long pos = base + off + lanes_below(b);
+            if (pos < (unsigned long long)a.emit.capacity) {
+                a.emit.i[pos] = (int32_t)(job.Ra * ROWBLK + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
+                a.emit.j[pos] = (int32_t)j;
+                a.emit.score[pos] = vs[r];
+            }
+        }
+        off += (unsigned long long)__popcll(b);
+    }
+}
+
 // Persistent ping-pong kernel.  A workgroup is two groups of four waves, one
 // wave of each group per SIMD.  At phase ph the group of parity ph runs the
 // MFMA contraction of the workgroup's tile ph while the other group runs the
@@ -336,7 +415,8 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
             }
         } else if (job.active) {
             if constexpr (OP == OP_FWD) epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
-            else bwd_epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
+            else if constexpr (OP == OP_BWD) bwd_epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
+            else thr_epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
             job.active = 0;
         }
     }
@@ -346,6 +426,11 @@ template <int MODE>
 static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, int op)
 {
     dim3 g((unsigned)grid), b(512);
+    if (op == OP_THR) {
+        if (a.kind != TK_SYM) return hipErrorInvalidValue;
+        tile_kernel<MODE, TK_SYM, OP_THR><<<g, b, 0, s>>>(a);
+        return hipGetLastError();
+    }
     if (op == OP_BWD) {
         if (a.kind == TK_SYM) tile_kernel<MODE, TK_SYM, OP_BWD><<<g, b, 0, s>>>(a);
         else if (a.kind == TK_RECT) tile_kernel<MODE, TK_RECT, OP_BWD><<<g, b, 0, s>>>(a);
