@@ -34,9 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = ("all-vs-all cRMSD pairs/s (N=20k,L=150); MFMA util; max err vs FP64 oracle (Å)")
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp64": 78.6}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x4": 2500.0, "fp64": 78.6}
 HBM_PEAK_GBS = 8000.0
-KBLOCK = {"fp32": 8, "bf16": 16, "fp16": 16, "fp64": 1}
+KBLOCK = {"fp32": 8, "bf16": 16, "fp16": 16, "bf16x4": 16, "fp64": 1}
 KERNEL_SOURCES = ["paper_1302_4000_amd/csrc/tile.hip", "paper_1302_4000_amd/csrc/eq2.h",
                   "paper_1302_4000_amd/csrc/internal.h"]
 
@@ -74,7 +74,7 @@ def issued_mfma_flops(prec: str, N: int, L: int) -> float:
     nb = Np // 64
     T = nb * (nb + 1) // 2
     waves = 4 * T - nb          # the wave below the diagonal of a diagonal tile idles
-    prod = 3 if prec in ("bf16", "fp16") else 1
+    prod = {"bf16": 3, "fp16": 3, "bf16x4": 4}.get(prec, 1)
     return waves * 32 * 32 * 9 * Lp * 2.0 * prod
 
 
@@ -286,6 +286,17 @@ def main():
                    mfma_util=fl / (cmp_res["tile_ms"] * 1e-3) / (PEAK_TFLOPS["fp32"] * 1e12),
                    algorithmic_tflops=18.0 * L * P / (cmp_res["tile_ms"] * 1e-3) / 1e12)
         outs["fp32"] = cmp_out
+    variants = {}
+    if not args.no_compare and prec == "bf16":
+        for vp in ("fp16", "bf16x4"):
+            steps = max(2, args.steps // 3)
+            log(f"[bench] {vp} variant: steps {steps}")
+            vres, vout = time_path(cl, torch, x, vp, steps, 1)
+            vres["mfma_util"] = issued_mfma_flops(vp, N, L) / (vres["tile_ms"] * 1e-3) / (
+                PEAK_TFLOPS[vp] * 1e12)
+            log(f"[bench] {vp}: {vres}")
+            variants[vp] = vres
+            outs[vp] = vout
 
     extra = {}
     if not args.no_extra:
@@ -332,6 +343,7 @@ def main():
         "roofline": roof,
         "max_err_A": errs,
         "fp32_path": cmp,
+        "split_variants": variants or None,
         "cpu_baseline": cpu,
         **extra,
     }

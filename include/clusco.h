@@ -63,12 +63,16 @@ typedef enum {
  *                                                          tolerance 5e-4 A
  *   SPLIT_FP16  the same split in float16 (|coordinate| < 65504 A).
  *                                                          tolerance 1e-4 A
- *   FP64        FP64 products and accumulation.           tolerance 1e-6 A */
+ *   FP64        FP64 products and accumulation.           tolerance 1e-6 A
+ *   SPLIT_BF16X4  the bfloat16 split with the fourth product lo*lo' as well
+ *               (no dropped term; fewer pairs need the fix-up).
+ *                                                          tolerance 5e-4 A */
 typedef enum {
     CLUSCO_FP32 = 0,
     CLUSCO_SPLIT_BF16 = 1,
     CLUSCO_SPLIT_FP16 = 2,
-    CLUSCO_FP64 = 3
+    CLUSCO_FP64 = 3,
+    CLUSCO_SPLIT_BF16X4 = 4
 } clusco_precision;
 
 typedef struct clusco_ctx *clusco_handle;

@@ -34,8 +34,8 @@ struct BatchPlan {
 
 struct clusco_ctx {
     int device;
-    double tol[4];   // fix-up tolerance per precision (A); <= 0 disables
-    double eps[4];   // calibrated relative error of the contraction per precision
+    double tol[NMODES];   // fix-up tolerance per precision (A); <= 0 disables
+    double eps[NMODES];   // calibrated relative error of the contraction per precision
     std::string last_error;
     // stage timing (measurement only): 4 events per recorded call
     std::vector<hipEvent_t> events;
@@ -68,7 +68,8 @@ clusco_status hip_fail(clusco_handle h, hipError_t e, const char *where)
 
 bool valid_precision(clusco_precision p)
 {
-    return p == CLUSCO_FP32 || p == CLUSCO_SPLIT_BF16 || p == CLUSCO_SPLIT_FP16 || p == CLUSCO_FP64;
+    return p == CLUSCO_FP32 || p == CLUSCO_SPLIT_BF16 || p == CLUSCO_SPLIT_FP16 || p == CLUSCO_FP64 ||
+           p == CLUSCO_SPLIT_BF16X4;
 }
 
 int mode_of(clusco_precision p)
@@ -76,6 +77,7 @@ int mode_of(clusco_precision p)
     switch (p) {
     case CLUSCO_FP32: return MODE_FP32;
     case CLUSCO_SPLIT_BF16: return MODE_BF16;
+    case CLUSCO_SPLIT_BF16X4: return MODE_BF16X4;
     case CLUSCO_SPLIT_FP16: return MODE_FP16;
     default: return MODE_FP64;
     }
@@ -136,6 +138,7 @@ ModelSet make_set(int mode, int64_t X, int64_t N, int64_t L, int64_t model0, int
     s.use_b = use_b;
     s.E = (int64_t)take(o, sizeof(double) * s.Np);
     s.cen = (int64_t)take(o, sizeof(double) * 3 * s.Np);
+    s.E64 = (int64_t)take(o, sizeof(double) * s.Np);
     s.ops = (int64_t)take(o, op_bytes_per_model(mode, s.Lp) * s.Np);
     return s;
 }
@@ -157,6 +160,8 @@ Problem make_problem(const ModelSet &A, const ModelSet &B, int sym, double coef)
     p.EB = B.E;
     p.cenA = A.cen;
     p.cenB = B.cen;
+    p.E64A = A.E64;
+    p.E64B = B.E64;
     p.XA = A.X;
     p.XB = B.X;
     p.flag_coef = coef;
@@ -491,10 +496,12 @@ clusco_status clusco_create(clusco_handle *h, int device)
     c->device = device;
     c->tol[MODE_FP32] = 1e-4;
     c->tol[MODE_BF16] = 5e-4;
+    c->tol[MODE_BF16X4] = 5e-4;
     c->tol[MODE_FP16] = 1e-4;
     c->tol[MODE_FP64] = 1e-6;
     c->eps[MODE_FP32] = 3e-7;
     c->eps[MODE_BF16] = 7e-7;
+    c->eps[MODE_BF16X4] = 2e-7;
     c->eps[MODE_FP16] = 1.6e-7;
     c->eps[MODE_FP64] = 0.0;
     *h = c;

@@ -6,8 +6,7 @@
 // below flag_coef (E_i + E_j); this kernel re-evaluates that test on the
 // stored scores of each listed block, compacts the flagged pairs in LDS and
 // recomputes each one from the raw float32 coordinates entirely in FP64
-// (centring with the FP64 centroids, H and both radii accumulated in FP64,
-// then the same Eq. 2 epilogue).  With `all` set (FP64 precision) every pair
+// (see pair_fp64), then the same Eq. 2 epilogue.  With `all` set (FP64 precision) every pair
 // of every block is computed this way.  In threshold mode the candidates are
 // the pairs the tile kernel marked in the block's ownership mask, and the
 // recomputed pairs below the cutoff are appended to the output arrays.
@@ -16,33 +15,52 @@
 
 namespace clusco {
 
+// cRMSD of one pair entirely in FP64 from the raw float32 coordinates:
+// H = sum_l x_l y_l^T - L c_x c_y^T (the centred correlation; in FP64 the
+// cancellation against translations of ~100 A costs about one digit) and
+// the exact FP64 radii computed once per model by the prep pass.
 __device__ __forceinline__ float pair_fp64(const float *xi, const float *xj, const double *ci,
-                                           const double *cj, int64_t L)
+                                           const double *cj, double ea, double eb, int64_t L)
 {
-    const double ci0 = ci[0], ci1 = ci[1], ci2 = ci[2];
-    const double cj0 = cj[0], cj1 = cj[1], cj2 = cj[2];
     double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double ea = 0.0, eb = 0.0;
-    for (int64_t l = 0; l < L; ++l) {
-        const double a0 = (double)xi[3 * l] - ci0, a1 = (double)xi[3 * l + 1] - ci1,
-                     a2 = (double)xi[3 * l + 2] - ci2;
-        const double b0 = (double)xj[3 * l] - cj0, b1 = (double)xj[3 * l + 1] - cj1,
-                     b2 = (double)xj[3 * l + 2] - cj2;
-        h[0] += a0 * b0; h[1] += a0 * b1; h[2] += a0 * b2;
-        h[3] += a1 * b0; h[4] += a1 * b1; h[5] += a1 * b2;
-        h[6] += a2 * b0; h[7] += a2 * b1; h[8] += a2 * b2;
-        ea += a0 * a0 + a1 * a1 + a2 * a2;
-        eb += b0 * b0 + b1 * b1 + b2 * b2;
+    int64_t l = 0;
+    for (; l + 1 < L; l += 2) {
+        double a[6], b[6];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            a[u] = (double)xi[3 * l + u];
+            b[u] = (double)xj[3 * l + u];
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                h[3 * p + q] = fma(a[p], b[q], fma(a[3 + p], b[3 + q], h[3 * p + q]));
     }
+    if (l < L) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                h[3 * p + q] = fma((double)xi[3 * l + p], (double)xj[3 * l + q], h[3 * p + q]);
+    }
+    const double dl = (double)L;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) h[3 * p + q] = fma(-dl * ci[p], cj[q], h[3 * p + q]);
     const double lr2 = eq2_lrmsd2(h, ea, eb);
-    return (float)sqrt(fmax(lr2 / (double)L, 0.0));
+    return (float)sqrt(fmax(lr2 / dl, 0.0));
 }
 
-__global__ __launch_bounds__(64) void fixup_kernel(FixupLaunch a)
+// One workgroup of FIX_THREADS per listed block at a time.
+constexpr int FIX_THREADS = 256;
+
+__global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
 {
     __shared__ uint16_t todo[ROWBLK * ROWBLK];
     __shared__ int cnt;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int64_t n = a.all ? a.n_all : (int64_t)a.counters[0];
     for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
         int e = 0;
@@ -70,9 +88,9 @@ __global__ __launch_bounds__(64) void fixup_kernel(FixupLaunch a)
         const double *EA = (const double *)(a.ws + p.EA);
         const double *EB = (const double *)(a.ws + p.EB);
         float *out = a.out + p.out;
-        if (lane == 0) cnt = 0;
+        if (tid == 0) cnt = 0;
         __syncthreads();
-        for (int q = lane; q < ROWBLK * ROWBLK; q += 64) {
+        for (int q = tid; q < ROWBLK * ROWBLK; q += FIX_THREADS) {
             const int64_t i = Ra * ROWBLK + (q >> 5), j = Rb * ROWBLK + (q & 31);
             const bool live = p.sym ? (i < j && j < NA) : (i < NA && j < NB);
             if (live) {
@@ -93,15 +111,18 @@ __global__ __launch_bounds__(64) void fixup_kernel(FixupLaunch a)
         const float *XA = a.XA + p.XA, *XB = a.XB + p.XB;
         const double *cenA = (const double *)(a.ws + p.cenA);
         const double *cenB = (const double *)(a.ws + p.cenB);
-        for (int s0 = 0; s0 < m; s0 += 64) {   // uniform trip count (ballots below)
-            const int s = s0 + lane;
+        const double *E64A = (const double *)(a.ws + p.E64A);
+        const double *E64B = (const double *)(a.ws + p.E64B);
+        for (int s0 = 0; s0 < m; s0 += FIX_THREADS) {   // uniform trip count (ballots below)
+            const int s = s0 + tid;
             int64_t i = 0, j = 0;
             float v = 0.0f;
             if (s < m) {
                 const int q = todo[s];
                 i = Ra * ROWBLK + (q >> 5);
                 j = Rb * ROWBLK + (q & 31);
-                v = pair_fp64(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j, L);
+                v = pair_fp64(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j, E64A[i],
+                              E64B[j], L);
                 if (!a.thr) out[p.sym ? packed_index(i, j, NA) : i * NB + j] = v;
             }
             if (a.thr) {
@@ -130,9 +151,9 @@ __global__ __launch_bounds__(64) void fixup_kernel(FixupLaunch a)
 
 hipError_t launch_fixup(const FixupLaunch &a, hipStream_t s)
 {
-    int64_t grid = a.all ? (a.n_all < 65536 ? a.n_all : 65536) : 2048;
+    int64_t grid = a.all ? (a.n_all < 65536 ? a.n_all : 65536) : 4096;
     if (grid < 1) grid = 1;
-    fixup_kernel<<<dim3((unsigned)grid), dim3(64), 0, s>>>(a);
+    fixup_kernel<<<dim3((unsigned)grid), dim3(FIX_THREADS), 0, s>>>(a);
     return hipGetLastError();
 }
 

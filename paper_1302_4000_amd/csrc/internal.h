@@ -30,7 +30,15 @@ namespace clusco {
 // zeros to a multiple of the K-block (Lp).  Zero padding is exact because it
 // is applied after centring and the scale 1/L uses the true L.
 
-enum Mode { MODE_FP32 = 0, MODE_BF16 = 1, MODE_FP16 = 2, MODE_FP64 = 3 };
+enum Mode { MODE_FP32 = 0, MODE_BF16 = 1, MODE_FP16 = 2, MODE_FP64 = 3, MODE_BF16X4 = 4 };
+constexpr int NMODES = 5;
+
+// split modes: hi/lo operand halves of bfloat16 (or float16) type
+__host__ __device__ constexpr bool is_split(int mode)
+{
+    return mode == MODE_BF16 || mode == MODE_FP16 || mode == MODE_BF16X4;
+}
+__host__ __device__ constexpr bool is_bf16(int mode) { return mode == MODE_BF16 || mode == MODE_BF16X4; }
 
 constexpr int ROWBLK = 32;   // models per MFMA row block
 constexpr int TILE = 64;     // models per workgroup tile edge (2x2 waves)
@@ -110,7 +118,7 @@ __host__ __device__ inline void band_decode_rect(int64_t t, int64_t na, int64_t 
 __host__ inline size_t op_bytes_per_model(int mode, int64_t Lp)
 {
     if (mode == MODE_FP32) return sizeof(float) * 3 * Lp;
-    if (mode == MODE_BF16 || mode == MODE_FP16) return 2 * 2 * 3 * Lp;
+    if (is_split(mode)) return 2 * 2 * 3 * Lp;
     return 0;
 }
 
@@ -129,6 +137,7 @@ struct ModelSet {
     int64_t ops;          // byte offset of the operand chunks in the workspace
     int64_t E;            // byte offset of the radii (double [Np])
     int64_t cen;          // byte offset of the centroids (double [Np][3])
+    int64_t E64;          // byte offset of the exact FP64 radii of the raw coordinates
     int32_t use_b;        // coordinates come from the second base pointer
     int32_t pad;
 };
@@ -140,6 +149,7 @@ struct Problem {
     int64_t tile0;        // first 64x64 tile of this problem in the launch
     int64_t wtile0;       // first 32x32 block of this problem in the launch
     int64_t opsA, opsB, EA, EB, cenA, cenB;   // workspace byte offsets
+    int64_t E64A, E64B;   // exact FP64 radii (fix-up)
     int64_t XA, XB;       // float offsets into the first / second coordinate base
     int64_t out;          // float offset into the output base
     double flag_coef;     // flag a pair when score < flag_coef (E_i + E_j); <= 0 never

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
     const float *x = (s.use_b ? a.XB : a.XA) + s.X + (real ? m : 0) * L * 3;
     double *E = (double *)(a.ws + s.E);
     double *cen = (double *)(a.ws + s.cen);
+    double *E64 = (double *)(a.ws + s.E64);
 
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
     if (real) {
@@ -66,6 +67,17 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
         cen[3 * m + 1] = c1;
         cen[3 * m + 2] = c2;
     }
+    // exact FP64 radius of the raw coordinates (used by the FP64 fix-up)
+    double e64 = 0.0;
+    if (real) {
+        for (int64_t l = lane; l < L; l += 64) {
+            const double d0 = (double)x[3 * l] - c0, d1 = (double)x[3 * l + 1] - c1,
+                         d2 = (double)x[3 * l + 2] - c2;
+            e64 += d0 * d0 + d1 * d1 + d2 * d2;
+        }
+        e64 = wave_sum(e64);
+    }
+    if (lane == 0) E64[m] = e64;
     if (MODE == MODE_FP64) {
         if (lane == 0) E[m] = 0.0;
         return;
@@ -93,7 +105,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
                 const int64_t lo_idx = (base + 64 + r + 32 * h) * 8 + el;
                 uint16_t *ops = (uint16_t *)(a.ws + s.ops);
                 double hv, lv;
-                if (MODE == MODE_BF16) {
+                if (is_bf16(MODE)) {
                     const uint16_t hb = bf16_bits_rn((float)v);
                     hv = (double)bf16_bits_to_float(hb);
                     const uint16_t lb = bf16_bits_rn((float)(v - hv));
@@ -124,6 +136,7 @@ hipError_t launch_prep(const PrepLaunch &a, hipStream_t s)
     case MODE_FP32: prep_kernel<MODE_FP32><<<grid, block, 0, s>>>(a); break;
     case MODE_BF16: prep_kernel<MODE_BF16><<<grid, block, 0, s>>>(a); break;
     case MODE_FP16: prep_kernel<MODE_FP16><<<grid, block, 0, s>>>(a); break;
+    case MODE_BF16X4: prep_kernel<MODE_BF16><<<grid, block, 0, s>>>(a); break;
     default: prep_kernel<MODE_FP64><<<grid, block, 0, s>>>(a); break;
     }
     return hipGetLastError();

@@ -34,7 +34,7 @@ __device__ __forceinline__ void pin_order() { asm volatile("" ::: "memory"); }
 template <int MODE>
 __device__ __forceinline__ f32x16 mfma_split(u32x4 a, u32x4 b, f32x16 c)
 {
-    if constexpr (MODE == MODE_BF16)
+    if constexpr (is_bf16(MODE))
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
     else
@@ -119,6 +119,14 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
                     acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
+            if constexpr (MODE == MODE_BF16X4) {
+                // fourth product lo*lo': the split then carries no dropped term
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        acc[3 * c + d] = mfma_split<MODE>(Al[c], Bl[d], acc[3 * c + d]);
+            }
             pin_order();
 #pragma unroll
             for (int d = 0; d < 3; ++d) Bl[d] = pb[nx + (2 * d + 1) * 64];
@@ -460,6 +468,7 @@ hipError_t launch_tile(int mode, const TileLaunch &a, hipStream_t s, int op)
     case MODE_FP32: return launch_mode<MODE_FP32>(a, s, grid, op);
     case MODE_BF16: return launch_mode<MODE_BF16>(a, s, grid, op);
     case MODE_FP16: return launch_mode<MODE_FP16>(a, s, grid, op);
+    case MODE_BF16X4: return launch_mode<MODE_BF16X4>(a, s, grid, op);
     default: return hipErrorInvalidValue;
     }
 }

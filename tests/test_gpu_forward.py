@@ -12,7 +12,7 @@ from paper_1302_4000_amd import synth
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "fp64": 1e-6}
+TOL = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "fp64": 1e-6, "bf16x4": 5e-4}
 
 
 @pytest.fixture(scope="module")
@@ -20,7 +20,7 @@ def cl():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1302_4000_amd as m
-    for p, t in (("fp32", 1e-4), ("bf16", 5e-4), ("fp16", 1e-4), ("fp64", 1e-6)):
+    for p, t in TOL.items():
         m.set_tolerance(p, t)
     return m
 
@@ -36,7 +36,7 @@ def run(cl, x, prec):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp64", "bf16x4"])
 def test_n200_l100_all_pairs(cl, prec):
     say(f"[parity] N=200 L=100 all pairs, {prec}")
     x = synth.workload("n200_l100")
@@ -61,7 +61,7 @@ def test_ragged_shapes(cl, N, L, prec):
     assert np.abs(got - want).max() < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x4"])
 def test_degenerate_models(cl, prec):
     say(f"[parity] degenerate models {prec}")
     rng = np.random.default_rng(0)
@@ -135,7 +135,7 @@ def test_n5000_l300_sampled(cl, prec):
     assert err.max() < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x4"])
 def test_n20000_l150_sampled(cl, prec):
     say(f"[parity] N=20000 L=150 sampled, {prec}")
     x = synth.workload("n20000_l150")
