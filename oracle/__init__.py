@@ -6,7 +6,8 @@ its Python binding) never imports it, and this package never imports the
 product.  The arithmetic lives in ``crmsd_oracle.c`` (plain C, FP64, OpenMP):
 the definition of cRMSD (Algorithms, Eq. 1) evaluated with an explicit Kabsch
 superposition (one-sided Jacobi SVD of the 3x3 correlation matrix, proper
-rotation, explicit residual).  Every function takes float32 or float64
+rotation, explicit residual), and the definition of dRMSD (Algorithms, Eq. 5)
+as a direct sum over atom pairs.  Every function takes float32 or float64
 coordinates and promotes them exactly to float64.
 
 Parity status: pinned (see ``tests/test_oracle_*.py``: invariants, closed
@@ -60,9 +61,13 @@ def _load():
     lib.oracle_crmsd_matrix_grad.argtypes = [dp, i64, i64, dp, dp, cint]
     lib.oracle_crmsd_cross_grad.argtypes = [dp, i64, dp, i64, i64, dp, dp, dp, cint]
     lib.oracle_crmsd_matrix_grad_rows.argtypes = [dp, i64, i64, dp, lp, i64, dp, cint]
+    lib.oracle_drmsd_pair.restype = ctypes.c_double
+    lib.oracle_drmsd_pair.argtypes = [dp, dp, i64]
+    lib.oracle_drmsd_matrix.argtypes = [dp, i64, i64, dp, cint]
+    lib.oracle_drmsd_pairs.argtypes = [dp, i64, i64, lp, lp, i64, dp, cint]
     for f in ("oracle_crmsd_matrix", "oracle_crmsd_pairs", "oracle_crmsd_cross",
               "oracle_crmsd_grad_pair", "oracle_crmsd_matrix_grad", "oracle_crmsd_cross_grad",
-              "oracle_crmsd_matrix_grad_rows"):
+              "oracle_crmsd_matrix_grad_rows", "oracle_drmsd_matrix", "oracle_drmsd_pairs"):
         getattr(lib, f).restype = cint
     _lib = lib
     return lib
@@ -172,6 +177,35 @@ def crmsd_cross_grad(a, b, g, threads: int = 0):
     _check(_load().oracle_crmsd_cross_grad(_p(a), a.shape[0], _p(b), b.shape[0], a.shape[1],
                                            _p(g), _p(gA), _p(gB), threads), "crmsd_cross_grad")
     return gA, gB
+
+
+def drmsd(a, b) -> float:
+    """Distance RMSD (Eq. 5) of two [L,3] models."""
+    a, b = _d(a), _d(b)
+    assert a.shape == b.shape and a.ndim == 2 and a.shape[1] == 3
+    return float(_load().oracle_drmsd_pair(_p(a), _p(b), a.shape[0]))
+
+
+def drmsd_matrix(x, threads: int = 0) -> np.ndarray:
+    """Packed all-vs-all dRMSD of an [N,L,3] ensemble."""
+    x = _d(x)
+    N, L = x.shape[0], x.shape[1]
+    out = np.zeros(N * (N - 1) // 2)
+    _check(_load().oracle_drmsd_matrix(_p(x), N, L, _p(out), threads), "drmsd_matrix")
+    return out
+
+
+def drmsd_pairs(x, I, J, threads: int = 0) -> np.ndarray:
+    """dRMSD of selected pairs (I[p], J[p]) of one ensemble."""
+    x = _d(x)
+    I = np.ascontiguousarray(I, dtype=np.int64)
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    out = np.zeros(I.shape[0])
+    lp = ctypes.POINTER(ctypes.c_int64)
+    _check(_load().oracle_drmsd_pairs(_p(x), x.shape[0], x.shape[1], I.ctypes.data_as(lp),
+                                      J.ctypes.data_as(lp), I.shape[0], _p(out), threads),
+           "drmsd_pairs")
+    return out
 
 
 def packed_index(i, j, N):

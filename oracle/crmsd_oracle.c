@@ -411,3 +411,54 @@ int oracle_crmsd_cross_grad(const double *A, int64_t Na, const double *B, int64_
     free(Cb);
     return 0;
 }
+
+
+/* ------------------------------------------------------------------ dRMSD
+ * Distance RMSD (Algorithms, Eq. 5): the RMS difference of the two models'
+ * intra-model distance matrices over the atom pairs i < j,
+ *     dRMSD = sqrt( 2/(L(L-1)) sum_{i<j} (d^A_ij - d^B_ij)^2 ),
+ * evaluated directly in FP64 (no Gram-matrix identity).  0 for L < 2. */
+double oracle_drmsd_pair(const double *A, const double *B, int64_t L)
+{
+    if (L < 2) return 0.0;
+    double s = 0.0;
+    for (int64_t i = 0; i < L; ++i) {
+        for (int64_t j = i + 1; j < L; ++j) {
+            double da = 0.0, db = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double u = A[3 * i + k] - A[3 * j + k], v = B[3 * i + k] - B[3 * j + k];
+                da += u * u;
+                db += v * v;
+            }
+            double d = sqrt(da) - sqrt(db);
+            s += d * d;
+        }
+    }
+    return sqrt(2.0 * s / ((double)L * (double)(L - 1)));
+}
+
+int oracle_drmsd_matrix(const double *X, int64_t N, int64_t L, double *out, int nthreads)
+{
+    if (N < 0 || L < 1) return 1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t base = i * (2 * N - i - 1) / 2 - i - 1;
+        for (int64_t j = i + 1; j < N; ++j)
+            out[base + j] = oracle_drmsd_pair(X + 3 * L * i, X + 3 * L * j, L);
+    }
+    return 0;
+}
+
+int oracle_drmsd_pairs(const double *X, int64_t N, int64_t L, const int64_t *I, const int64_t *J,
+                       int64_t P, double *out, int nthreads)
+{
+    if (N < 0 || L < 1 || P < 0) return 1;
+    for (int64_t p = 0; p < P; ++p)
+        if (I[p] < 0 || I[p] >= N || J[p] < 0 || J[p] >= N) return 2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < P; ++p)
+        out[p] = oracle_drmsd_pair(X + 3 * L * I[p], X + 3 * L * J[p], L);
+    return 0;
+}

@@ -27,6 +27,16 @@ MUTANTS = {
     "ascending_sort": ("if (n[ord[b]] > n[ord[a]])", "if (n[ord[b]] < n[ord[a]])"),
 }
 
+DRMSD_MUTANTS = {
+    "squared_distance": ("double d = sqrt(da) - sqrt(db);", "double d = da - db;"),
+    "wrong_pair_count": ("return sqrt(2.0 * s / ((double)L * (double)(L - 1)));",
+                         "return sqrt(s / ((double)L * (double)(L - 1)));"),
+    "skips_neighbours": ("for (int64_t j = i + 1; j < L; ++j) {\n            double da",
+                         "for (int64_t j = i + 2; j < L; ++j) {\n            double da"),
+    "one_coordinate": ("for (int k = 0; k < 3; ++k) {\n                double u",
+                       "for (int k = 0; k < 2; ++k) {\n                double u"),
+}
+
 
 def build_variant(tmp_path, name, src):
     c = tmp_path / f"{name}.c"
@@ -88,3 +98,42 @@ def test_mutant_is_caught(tmp_path, name):
     assert src.count(old) == 1, "mutation site moved; update the test"
     failed = pins_hold(build_variant(tmp_path, name, src.replace(old, new)))
     assert failed, f"mutant {name} passed every pin"
+
+
+def drmsd_pins_hold(tmp_path, name, src):
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(src)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", str(so),
+                    str(c), "-lm"], check=True)
+    lib = ctypes.CDLL(str(so))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_drmsd_pair.restype = ctypes.c_double
+    lib.oracle_drmsd_pair.argtypes = [dp, dp, ctypes.c_int64]
+
+    def drmsd(a, b):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        return lib.oracle_drmsd_pair(a.ctypes.data_as(dp), b.ctypes.data_as(dp), a.shape[0])
+    failed = []
+    A, B = np.array([[0, 0, 0], [3.0, 0, 0]]), np.array([[1, 1, 1], [1, 1, 5.0]])
+    if abs(drmsd(A, B) - 1.0) > 1e-12:
+        failed.append("two_atoms")
+    L = 10
+    A = np.arange(L)[:, None] * 3.8 * np.array([0, 0, 1.0])
+    B = np.arange(L)[:, None] * 3.1 * np.array([0, 0, 1.0])
+    if abs(drmsd(A, B) - 0.7 * np.sqrt(L * (L + 1) / 6.0)) > 1e-11:
+        failed.append("collinear")
+    return failed
+
+
+def test_unmodified_drmsd_passes(tmp_path):
+    assert drmsd_pins_hold(tmp_path, "orig_d", open(SRC).read()) == []
+
+
+@pytest.mark.parametrize("name", sorted(DRMSD_MUTANTS))
+def test_drmsd_mutant_is_caught(tmp_path, name):
+    old, new = DRMSD_MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site moved; update the test"
+    assert drmsd_pins_hold(tmp_path, name, src.replace(old, new)), f"mutant {name} passed"
