@@ -220,6 +220,57 @@ def threshold_leg(cl, torch, x, steps):
     return res
 
 
+def drmsd_leg(cl, torch, x, x_np, steps, with_error):
+    """All-vs-all dRMSD (Eq. 5) on the same ensemble: a Gram product over
+    K = L(L-1)/2 distance deviations per model.  Algorithmic work 2 K flops
+    per pair (one length-K dot product); issued 3x (split) on MFMA."""
+    import numpy as np
+    N, L = x.shape[0], x.shape[1]
+    P = N * (N - 1) // 2
+    K = L * (L - 1) // 2
+    res = {"K": K}
+    for prec in ("bf16",):
+        out = torch.empty(P, dtype=torch.float32, device=x.device)
+        ws = torch.empty(cl.drmsd_workspace_size(N, L, prec), dtype=torch.uint8, device=x.device)
+        cl.drmsd_matrix(x, prec, out=out, ws=ws)
+        torch.cuda.synchronize()
+        dev = x.device.index
+        cl.binding.stage_timing(dev, steps)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cl.drmsd_matrix(x, prec, out=out, ws=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st, n = cl.binding.stage_times(dev)
+        cl.binding.stage_timing(dev, 0)
+        assert n == steps
+        tile_ms = st[1] / steps
+        alg = 2.0 * K * P
+        r = {"ms_per_call": ms, "pairs_per_s": P / (ms * 1e-3),
+             "stages_ms": {"prep_ms": st[0] / steps, "tile_ms": tile_ms,
+                           "fixup_ms": st[2] / steps},
+             "fixup_blocks": cl.fixup_count(ws),
+             "tile_algorithmic_tflops": alg / (tile_ms * 1e-3) / 1e12,
+             "tile_frac_of_bf16_peak": alg / (tile_ms * 1e-3) / (PEAK_TFLOPS["bf16"] * 1e12),
+             "tile_mfma_util": 3.0 * 2.0 * (-(-K // 16) * 16) * P / (tile_ms * 1e-3)
+             / (PEAK_TFLOPS["bf16"] * 1e12)}
+        if with_error:
+            import oracle
+            rng = np.random.default_rng(11)
+            i = rng.integers(0, N, 20000)
+            j = rng.integers(0, N, 20000)
+            k = i != j
+            I, J = np.minimum(i, j)[k], np.maximum(i, j)[k]
+            ii, jj = np.triu_indices(min(N, 50), 1)
+            I, J = np.r_[I, ii], np.r_[J, jj]
+            got = out[torch.from_numpy(oracle.packed_index(I, J, N)).to(x.device)].cpu().numpy()
+            r["max_err_A"] = float(np.abs(got.astype(np.float64) - oracle.drmsd_pairs(x_np, I, J)).max())
+            r["error_sample"] = f"{len(I)} pairs: uniform + all pairs of models 0-49"
+        res[prec] = r
+        del out, ws
+    return res
+
+
 def copy_calibration(nbytes: int):
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -306,6 +357,9 @@ def main():
         log("[bench] batched: 64 uneven ensembles")
         extra["batched"] = batched_leg(cl, torch, max(3, args.steps // 2))
         log(f"[bench] batched: {extra['batched']}")
+        log("[bench] dRMSD all-vs-all")
+        extra["drmsd"] = drmsd_leg(cl, torch, x, x_np, max(3, args.steps // 3), not args.no_error)
+        log(f"[bench] drmsd: {extra['drmsd']}")
         log("[bench] backward: N=4096 L=256")
         extra["backward"] = backward_leg(cl, torch, max(3, args.steps // 2))
         log(f"[bench] backward: {extra['backward']}")

@@ -199,6 +199,27 @@ clusco_status clusco_crmsd_cross_backward(clusco_handle h, const float *A, int64
                                           clusco_precision p, float *grad_A, float *grad_B,
                                           void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- dRMSD */
+
+/* Workspace bytes for clusco_drmsd_matrix (0 if invalid).  It grows as
+ * N * L(L-1)/2 * 4 bytes (the operand vectors) for the MFMA precisions. */
+size_t clusco_drmsd_workspace_size(clusco_handle h, int64_t N, int64_t L, clusco_precision p);
+
+/* All-vs-all distance RMSD (Algorithms, Eq. 5): for every pair i < j,
+ *     dRMSD(i, j) = sqrt( (2 / (L(L-1))) sum_{p<q} (|x^i_p - x^i_q| - |x^j_p - x^j_q|)^2 ),
+ * the RMS difference of the two models' intra-model distance matrices.  No
+ * superposition is involved and mirror images score zero.  Same layouts,
+ * packed output order, workspace and stream rules as clusco_crmsd_matrix.
+ * The FP32 / split precisions take the product of the distance-deviation
+ * vectors on MFMA (FP32 accumulation) and recompute in FP64 the pairs whose
+ * accumulation error could exceed the precision's tolerance; FP64 evaluates
+ * the definition in FP64 for every pair (slow: O(N^2 L^2)).  N in {0, 1}
+ * returns CLUSCO_OK with nothing enqueued; L = 1 gives zeros.
+ * L above 4096 returns CLUSCO_ERR_UNSUPPORTED. */
+clusco_status clusco_drmsd_matrix(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                  clusco_precision p, float *out, void *ws, size_t ws_bytes,
+                                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,8 @@ def lib():
             "clusco_set_tolerance": (st, [vp, st, d]),
             "clusco_crmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
+            "clusco_drmsd_workspace_size": (sz, [vp, i64, i64, st]),
+            "clusco_drmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_fixup_count": (st, [vp, vp, i64p, vp]),
             "clusco_stage_timing": (st, [vp, ctypes.c_int]),
             "clusco_stage_times": (st, [vp, ctypes.POINTER(ctypes.c_double),
@@ -160,6 +162,33 @@ def crmsd_matrix(x: torch.Tensor, precision="fp32", out: torch.Tensor | None = N
     rc = lib().clusco_crmsd_matrix(h, _ptr(x), N, L, p, _ptr(out), _ptr(ws), ws.numel(),
                                    _stream(dev))
     _check(rc, h, "clusco_crmsd_matrix")
+    return out
+
+
+def drmsd_workspace_size(N: int, L: int, precision="bf16", device: int = 0) -> int:
+    return int(lib().clusco_drmsd_workspace_size(handle(device), N, L, _prec(precision)))
+
+
+def drmsd_matrix(x: torch.Tensor, precision="bf16", out: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Packed all-vs-all dRMSD [N(N-1)/2] of x [N, L, 3] (float32, on the GPU)."""
+    x = _coords(x)
+    N, L = x.shape[0], x.shape[1]
+    dev = x.device
+    h = handle(dev.index)
+    p = _prec(precision)
+    need = int(lib().clusco_drmsd_workspace_size(h, N, L, p))
+    if need == 0:
+        raise ClucsoError(ERR_INVALID_ARG, "clusco_drmsd_workspace_size", f"N={N} L={L}")
+    ws = _workspace(need, dev, ws)
+    P = N * (N - 1) // 2
+    if out is None:
+        out = torch.empty(P, dtype=torch.float32, device=dev)
+    elif out.numel() != P or out.dtype != torch.float32 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float32 tensor of N(N-1)/2 elements")
+    rc = lib().clusco_drmsd_matrix(h, _ptr(x), N, L, p, _ptr(out), _ptr(ws), ws.numel(),
+                                   _stream(dev))
+    _check(rc, h, "clusco_drmsd_matrix")
     return out
 
 

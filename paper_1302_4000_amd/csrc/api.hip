@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <list>
 #include <string>
 #include <vector>
@@ -930,6 +931,117 @@ clusco_status clusco_crmsd_threshold(clusco_handle h, const float *coords, int64
         fl.n_all = problem_wtiles(t.s.p);
         e = launch_fixup(fl, st);
         if (e != hipSuccess) return hip_fail(h, e, "fp64 launch");
+    }
+    stage_mark(h, 3, st);
+    return CLUSCO_OK;
+}
+
+// ---------------------------------------------------------------- dRMSD
+
+namespace {
+
+constexpr int64_t MAX_DIST_L = 4096;   // atom pairs are packed as two 16-bit indices
+
+struct DistLayout {
+    DistLaunch d;
+    size_t total;
+};
+
+// Every non-FP64 mode accumulates the Gram products in FP32, one rounding per
+// MFMA step: K/2 steps (FP32), 3K/16 (split) or 4K/16 (split x4).  For a pair
+// of similar models the partial sums grow linearly to about E, so the
+// rounding errors add up to about eps E with eps = 2^-24 sqrt(steps / 3).  A
+// pair is flagged when eps (E_i + E_j) / (K score) could exceed tol / 2 (a
+// margin of four on the first-order score error eps (E_i + E_j) / (2 K score)).
+double dist_flag_coef(clusco_handle h, int mode, int64_t K)
+{
+    const double tol = h->tol[mode];
+    if (mode == MODE_FP64 || !(tol > 0.0) || K < 1) return -1.0;
+    const double steps = mode == MODE_FP32     ? K / 2.0
+                         : mode == MODE_BF16X4 ? K / 4.0
+                                               : 3.0 * K / 16.0;
+    const double eps = std::ldexp(1.0, -24) * std::sqrt(steps / 3.0);
+    return 2.0 * eps / ((double)K * tol);
+}
+
+DistLayout dist_layout(clusco_handle h, int mode, int64_t N, int64_t L)
+{
+    DistLayout r{};
+    DistLaunch &d = r.d;
+    d.N = N;
+    d.Np = round_up(N > 0 ? N : 1, TILE);
+    d.L = L;
+    d.K = L * (L - 1) / 2;
+    d.Kp = round_up(d.K > 0 ? d.K : 1, 16);
+    d.KB = d.Kp / kblock(mode == MODE_FP64 ? MODE_BF16 : mode);
+    d.nref = N < 256 ? N : 256;
+    d.nb = (d.Np + 127) / 128;
+    d.T = tri_count(d.nb);
+    d.nrb = d.Np / ROWBLK;
+    size_t o = 256;
+    d.off_c = (int64_t)take(o, sizeof(double) * d.Kp);
+    d.off_pq = (int64_t)take(o, sizeof(uint32_t) * d.Kp);
+    d.off_E = (int64_t)take(o, sizeof(double) * d.Np);
+    d.off_ops = mode == MODE_FP64 ? 0 : (int64_t)take(o, (size_t)4 * d.Np * d.Kp);
+    const size_t off_list = take(o, sizeof(FixEntry) * tri_count(d.nrb));
+    d.all = mode == MODE_FP64;
+    d.flag_coef = h ? dist_flag_coef(h, mode, d.K) : -1.0;
+    d.list = (FixEntry *)off_list;   // relative until the workspace is known
+    r.total = o;
+    return r;
+}
+
+} // namespace
+
+size_t clusco_drmsd_workspace_size(clusco_handle h, int64_t N, int64_t L, clusco_precision p)
+{
+    if (!h || N < 0 || N > MAX_N || L < 1 || L > MAX_DIST_L || !valid_precision(p)) return 0;
+    return dist_layout(h, mode_of(p), N, L).total;
+}
+
+clusco_status clusco_drmsd_matrix(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                  clusco_precision p, float *out, void *ws, size_t ws_bytes,
+                                  void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (N < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0 and L >= 1");
+    if (N > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
+    if (L > MAX_DIST_L) return fail(h, CLUSCO_ERR_UNSUPPORTED, "L above 4096");
+    if (N < 2) return CLUSCO_OK;
+    if (!coords || !out) return fail(h, CLUSCO_ERR_INVALID_ARG, "null coords or out");
+    if (!aligned(coords, 4) || !aligned(out, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "coords and out must be 4-byte aligned");
+    const int mode = mode_of(p);
+    DistLayout r = dist_layout(h, mode, N, L);
+    if (!ws || ws_bytes < r.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    hipStream_t st = (hipStream_t)stream;
+    if (L == 1) {
+        hipError_t e = launch_zero(out, N * (N - 1) / 2, st);
+        return e == hipSuccess ? CLUSCO_OK : hip_fail(h, e, "zero launch");
+    }
+    DistLaunch &d = r.d;
+    d.X = coords;
+    d.ws = (char *)ws;
+    d.out = out;
+    d.counters = (int *)ws;
+    d.list = (FixEntry *)((char *)ws + (size_t)d.list);
+    stage_mark(h, 0, st);
+    hipError_t e = launch_dist_prep(mode, d, st);
+    if (e != hipSuccess) return hip_fail(h, e, "dRMSD prep launch");
+    stage_mark(h, 1, st);
+    if (mode != MODE_FP64) {
+        e = launch_dist_tile(mode, d, st);
+        if (e != hipSuccess) return hip_fail(h, e, "dRMSD tile launch");
+    }
+    stage_mark(h, 2, st);
+    if (d.all || d.flag_coef > 0.0) {
+        e = launch_dist_fixup(d, st);
+        if (e != hipSuccess) return hip_fail(h, e, "dRMSD fix-up launch");
     }
     stage_mark(h, 3, st);
     return CLUSCO_OK;

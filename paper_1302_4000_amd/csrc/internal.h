@@ -254,6 +254,32 @@ struct FixupLaunch {
     Emit emit;
 };
 
+// All-vs-all dRMSD (Eq. 5) as a Gram matrix of distance-deviation vectors.
+// Workspace regions (byte offsets): the reference distance vector c (double
+// [Kp]), the atom pair of each distance index (uint32 p | q << 16, [Kp]), the
+// radii E (double [Np]) and the operand chunks ([Np/32][KB][planes][64 lanes]
+// as for one coordinate plane of the cRMSD layout).
+struct DistLaunch {
+    const float *X;       // raw coordinates [N][L][3]
+    char *ws;
+    float *out;           // packed [N(N-1)/2]
+    int64_t N, Np, L;
+    int64_t K, Kp, KB;    // distances per model, padded to the K-block, K-blocks
+    int64_t nref;         // models averaged into the reference vector
+    int64_t nb, T;        // 128-model tiles per side, tiles in the launch
+    int64_t nrb;          // 32-model row blocks per side
+    int64_t off_c, off_pq, off_E, off_ops;
+    int *counters;        // [0] fix-up list length (zeroed by the prep pass)
+    FixEntry *list;
+    double flag_coef;     // flag a pair when score < flag_coef (E_i + E_j); <= 0 never
+    int32_t all;          // 1: the fix-up recomputes every pair (FP64 precision)
+    int32_t pad;
+};
+
+hipError_t launch_dist_prep(int mode, const DistLaunch &a, hipStream_t s);
+hipError_t launch_dist_tile(int mode, const DistLaunch &a, hipStream_t s);
+hipError_t launch_dist_fixup(const DistLaunch &a, hipStream_t s);
+
 // Workspace of one launch: counters, then per-set regions, then the list.
 struct WsLayout {
     size_t total;

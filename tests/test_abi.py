@@ -167,3 +167,24 @@ def test_backward_argument_errors(L, h):
         binding.ERR_WORKSPACE
     assert g(h, None, 64, FAKE, 1, 40, FAKE, FAKE, 1, FAKE, FAKE, FAKE, needc, None) == \
         binding.ERR_INVALID_ARG
+
+
+def test_drmsd_sizes_and_argument_errors(L, h):
+    s = L.clusco_drmsd_workspace_size(h, 1000, 150, 1)
+    K = 150 * 149 // 2
+    assert s % 256 == 0 and s >= 4 * 1024 * K          # operand vectors, 4 bytes a value
+    assert L.clusco_drmsd_workspace_size(h, 1000, 150, 3) < 1024 * K   # FP64 keeps no operands
+    assert L.clusco_drmsd_workspace_size(h, 10, 4097, 1) == 0
+    assert L.clusco_drmsd_workspace_size(h, 10, 0, 1) == 0
+    f = L.clusco_drmsd_matrix
+    need = L.clusco_drmsd_workspace_size(h, 100, 50, 0)
+    assert f(None, FAKE, 100, 50, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 0, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, 7, FAKE, FAKE, need, None) == binding.ERR_UNSUPPORTED
+    assert f(h, FAKE, 100, 5000, 0, FAKE, FAKE, need, None) == binding.ERR_UNSUPPORTED
+    assert f(h, None, 100, 50, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE_ODD, 100, 50, 0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, 0, FAKE, FAKE, need - 1, None) == binding.ERR_WORKSPACE
+    assert f(h, FAKE, 100, 50, 0, FAKE, ctypes.c_void_p(0x10040), need, None) == \
+        binding.ERR_INVALID_ARG
+    assert f(h, None, 1, 50, 1, None, None, 0, None) == binding.OK
