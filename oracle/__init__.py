@@ -8,7 +8,9 @@ the definition of cRMSD (Algorithms, Eq. 1) evaluated with an explicit Kabsch
 superposition (one-sided Jacobi SVD of the 3x3 correlation matrix, proper
 rotation, explicit residual), and the definition of dRMSD (Algorithms, Eq. 5)
 as a direct sum over atom pairs.  Every function takes float32 or float64
-coordinates and promotes them exactly to float64.
+coordinates and promotes them exactly to float64.  ``kmedoids`` clusters a
+packed float32 score matrix (K-means with member centres, the representative
+by the smallest <R>/f) with exact integer sums.
 
 Parity status: pinned (see ``tests/test_oracle_*.py``: invariants, closed
 forms, library-routine equalities, brute force on tiny inputs, finite
@@ -65,6 +67,10 @@ def _load():
     lib.oracle_drmsd_pair.argtypes = [dp, dp, i64]
     lib.oracle_drmsd_matrix.argtypes = [dp, i64, i64, dp, cint]
     lib.oracle_drmsd_pairs.argtypes = [dp, i64, i64, lp, lp, i64, dp, cint]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.oracle_kmedoids.argtypes = [fp, i64, i64, i32p, i64, i32p, i32p, lp, dp, lp]
+    lib.oracle_kmedoids.restype = cint
     for f in ("oracle_crmsd_matrix", "oracle_crmsd_pairs", "oracle_crmsd_cross",
               "oracle_crmsd_grad_pair", "oracle_crmsd_matrix_grad", "oracle_crmsd_cross_grad",
               "oracle_crmsd_matrix_grad_rows", "oracle_drmsd_matrix", "oracle_drmsd_pairs"):
@@ -206,6 +212,32 @@ def drmsd_pairs(x, I, J, threads: int = 0) -> np.ndarray:
                                       J.ctypes.data_as(lp), I.shape[0], _p(out), threads),
            "drmsd_pairs")
     return out
+
+
+def kmedoids(D, N: int, k: int, init, max_iter: int = 100) -> dict:
+    """K-means over a packed float32 score matrix with members as centres
+    (K-medoids, alternating assignment / update), exact int64 sums of the
+    scores rounded to 2^-20, and the representative cluster by min <R>/f.
+    See the clustering section of crmsd_oracle.c for the exact rules."""
+    D = np.ascontiguousarray(D, dtype=np.float32)
+    assert D.shape == (N * (N - 1) // 2,)
+    init = np.ascontiguousarray(init, dtype=np.int32)
+    label = np.zeros(N, np.int32)
+    med = np.zeros(k, np.int32)
+    size = np.zeros(k, np.int64)
+    mean_r = np.zeros(k)
+    info = np.zeros(3, np.int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    rc = _load().oracle_kmedoids(D.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), N, k,
+                                 init.ctypes.data_as(i32p), max_iter, label.ctypes.data_as(i32p),
+                                 med.ctypes.data_as(i32p), size.ctypes.data_as(lp), _p(mean_r),
+                                 info.ctypes.data_as(lp))
+    _check(rc, "kmedoids")
+    rep = int(info[0])
+    return {"labels": label, "medoids": med, "sizes": size, "mean_r": mean_r,
+            "rep_cluster": rep, "representative": int(med[rep]) if rep >= 0 else -1,
+            "iterations": int(info[1]), "converged": bool(info[2])}
 
 
 def packed_index(i, j, N):

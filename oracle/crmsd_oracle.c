@@ -462,3 +462,113 @@ int oracle_drmsd_pairs(const double *X, int64_t N, int64_t L, const int64_t *I, 
         out[p] = oracle_drmsd_pair(X + 3 * L * I[p], X + 3 * L * J[p], L);
     return 0;
 }
+
+/* ------------------------------------------------------------- clustering
+ * K-means over the all-vs-all matrix (Implementation; Results and
+ * Discussion: K-means with k clusters, the representative chosen by the
+ * smallest <R>/f).  Only the N(N-1)/2 scores are given, so a cluster centre
+ * is one of its members (a medoid): the mean of models under cRMSD is not a
+ * function of the matrix.  Alternating steps, from caller-given distinct
+ * initial medoids:
+ *   assign  every model joins the cluster of its nearest medoid (exact
+ *           float32 comparison; ties to the lowest cluster index; a medoid
+ *           always joins its own cluster);
+ *   update  each cluster's new medoid is the member with the smallest sum of
+ *           scores to the other members (ties to the lowest model index);
+ * repeated until no medoid changes or max_iter updates have run (then one
+ * more assignment).  Sums are exact: each score is rounded once to a
+ * multiple of 2^-20 (q = rint(d 2^20), an integer) and summed in int64, so
+ * the decisions do not depend on summation order.  Scores must be finite,
+ * non-negative and below 2^22.
+ * Representative: n_c members, f = n_c / N, <R> = the mean score over the
+ * n_c (n_c - 1) / 2 pairs of cluster c (from the same exact sums); the
+ * representative cluster minimises <R> / f (clusters of one model are not
+ * eligible; ties to the lowest index) and its medoid is the representative
+ * model. */
+static double packed_at(const float *D, int64_t N, int64_t i, int64_t j)
+{
+    if (i == j) return 0.0;
+    if (i > j) { int64_t t = i; i = j; j = t; }
+    return (double)D[i * (2 * N - i - 1) / 2 + (j - i - 1)];
+}
+
+static int64_t quant(double d) { return (int64_t)nearbyint(d * 1048576.0); }
+
+static void km_assign(const float *D, int64_t N, int64_t k, const int32_t *med, int32_t *label)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t best = -1;
+        for (int64_t c = 0; c < k; ++c)
+            if (med[c] == i) { best = c; break; }
+        if (best < 0) {
+            double bd = 0.0;
+            for (int64_t c = 0; c < k; ++c) {
+                double d = packed_at(D, N, i, med[c]);
+                if (best < 0 || d < bd) { best = c; bd = d; }
+            }
+        }
+        label[i] = (int32_t)best;
+    }
+}
+
+/* cost[i] = sum over the other members j of i's cluster of q(D(i, j)). */
+static void km_costs(const float *D, int64_t N, const int32_t *label, int64_t *cost)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t s = 0;
+        for (int64_t j = 0; j < N; ++j)
+            if (j != i && label[j] == label[i]) s += quant(packed_at(D, N, i, j));
+        cost[i] = s;
+    }
+}
+
+int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, int64_t max_iter,
+                    int32_t *label, int32_t *medoid, int64_t *size, double *mean_r,
+                    int64_t *info)
+{
+    if (N < 1 || k < 1 || k > N || max_iter < 0) return 1;
+    for (int64_t c = 0; c < k; ++c) {
+        if (init[c] < 0 || init[c] >= N) return 2;
+        for (int64_t e = 0; e < c; ++e)
+            if (init[e] == init[c]) return 3;
+        medoid[c] = init[c];
+    }
+    int64_t *cost = malloc(sizeof(int64_t) * N);
+    if (!cost) return 4;
+    int64_t it = 0, converged = 0;
+    while (it < max_iter) {
+        km_assign(D, N, k, medoid, label);
+        km_costs(D, N, label, cost);
+        ++it;
+        int changed = 0;
+        for (int64_t c = 0; c < k; ++c) {
+            int64_t best = -1;
+            for (int64_t i = 0; i < N; ++i)
+                if (label[i] == c && (best < 0 || cost[i] < cost[best])) best = i;
+            if (best != medoid[c]) { medoid[c] = (int32_t)best; changed = 1; }
+        }
+        if (!changed) { converged = 1; break; }
+    }
+    if (!converged) {
+        km_assign(D, N, k, medoid, label);
+        km_costs(D, N, label, cost);
+    }
+    int64_t rep = -1;
+    double rep_score = 0.0;
+    for (int64_t c = 0; c < k; ++c) {
+        int64_t n = 0, s = 0;
+        for (int64_t i = 0; i < N; ++i)
+            if (label[i] == c) { ++n; s += cost[i]; }
+        size[c] = n;
+        mean_r[c] = n > 1 ? ((double)s / 1048576.0) / ((double)n * (double)(n - 1)) : 0.0;
+        if (n > 1) {
+            double score = mean_r[c] * ((double)N / (double)n);
+            if (rep < 0 || score < rep_score) { rep = c; rep_score = score; }
+        }
+    }
+    info[0] = rep;
+    info[1] = it;
+    info[2] = converged;
+    free(cost);
+    return 0;
+}

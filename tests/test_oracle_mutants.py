@@ -137,3 +137,52 @@ def test_drmsd_mutant_is_caught(tmp_path, name):
     src = open(SRC).read()
     assert src.count(old) == 1, "mutation site moved; update the test"
     assert drmsd_pins_hold(tmp_path, name, src.replace(old, new)), f"mutant {name} passed"
+
+
+KM_MUTANTS = {
+    "assign_ties_high": ("if (best < 0 || d < bd) { best = c; bd = d; }",
+                         "if (best < 0 || d <= bd) { best = c; bd = d; }"),
+    "update_max": ("(best < 0 || cost[i] < cost[best])", "(best < 0 || cost[i] > cost[best])"),
+    "mean_over_n2": ("((double)n * (double)(n - 1))", "((double)n * (double)n)"),
+    "no_fraction": ("double score = mean_r[c] * ((double)N / (double)n);",
+                    "double score = mean_r[c];"),
+    "cost_all_models": ("if (j != i && label[j] == label[i]) s +=", "if (j != i) s +="),
+}
+
+
+def kmedoids_pins_fail(tmp_path, name, src):
+    """Runs the K-medoids pin tests against a build of `src`; returns True if
+    any of them fails."""
+    import importlib
+    import oracle as orc_mod
+    so = tmp_path / f"{name}.so"
+    c = tmp_path / f"{name}.c"
+    c.write_text(src)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", str(so),
+                    str(c), "-lm"], check=True)
+    saved = orc_mod._lib, orc_mod._LIB
+    try:
+        orc_mod._lib, orc_mod._LIB = None, str(so)
+        t = importlib.import_module("test_oracle_kmedoids")
+        for fn in (t.test_separated_groups_medians_and_closed_forms, t.test_tie_rules,
+                   t.test_fixed_point_by_brute_force, t.test_k_equals_one_is_the_global_median,
+                   t.test_k_equals_n_and_argument_checks):
+            try:
+                fn(orc_mod)
+            except (AssertionError, ValueError):
+                return True
+        return False
+    finally:
+        orc_mod._lib, orc_mod._LIB = saved
+
+
+def test_unmodified_kmedoids_passes(tmp_path):
+    assert not kmedoids_pins_fail(tmp_path, "orig_k", open(SRC).read())
+
+
+@pytest.mark.parametrize("name", sorted(KM_MUTANTS))
+def test_kmedoids_mutant_is_caught(tmp_path, name):
+    old, new = KM_MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site moved; update the test"
+    assert kmedoids_pins_fail(tmp_path, name, src.replace(old, new)), f"mutant {name} passed"
