@@ -271,6 +271,25 @@ def drmsd_leg(cl, torch, x, x_np, steps, with_error):
     return res
 
 
+def kmedoids_leg(cl, torch, D, N, steps):
+    """K-means with member centres (k = 20, the paper's setting for decoy
+    sets) over the packed matrix the main path produced.  Each update pass
+    streams the whole packed matrix once: 4 bytes per pair per pass."""
+    k = 20
+    init = [(c * N) // k for c in range(k)]
+    ws = torch.empty(cl.binding.lib().clusco_cluster_workspace_size(
+        cl.binding.handle(D.device.index), N, k), dtype=torch.uint8, device=D.device)
+    r = cl.kmedoids(D, N, k, init, 100, ws=ws)
+    torch.cuda.synchronize()
+    ms = timed(torch, lambda: cl.kmedoids(D, N, k, init, 100, ws=ws), steps, 1)
+    info = r["info"].cpu().tolist()
+    passes = info[1] + (0 if info[2] else 1)
+    gbs = passes * 4.0 * D.numel() / (ms * 1e-3) / 1e9
+    return {"k": k, "ms_per_call": ms, "updates": info[1], "converged": bool(info[2]),
+            "representative_cluster": info[0],
+            "matrix_passes": passes, "matrix_stream_gbs": gbs, "frac_of_hbm_peak": gbs / 8000.0}
+
+
 def copy_calibration(nbytes: int):
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -357,6 +376,9 @@ def main():
         log("[bench] batched: 64 uneven ensembles")
         extra["batched"] = batched_leg(cl, torch, max(3, args.steps // 2))
         log(f"[bench] batched: {extra['batched']}")
+        log("[bench] K-means (member centres) on the packed matrix")
+        extra["kmedoids"] = kmedoids_leg(cl, torch, main_out, N, max(3, args.steps // 3))
+        log(f"[bench] kmedoids: {extra['kmedoids']}")
         log("[bench] dRMSD all-vs-all")
         extra["drmsd"] = drmsd_leg(cl, torch, x, x_np, max(3, args.steps // 3), not args.no_error)
         log(f"[bench] drmsd: {extra['drmsd']}")

@@ -220,6 +220,45 @@ clusco_status clusco_drmsd_matrix(clusco_handle h, const float *coords, int64_t 
                                   clusco_precision p, float *out, void *ws, size_t ws_bytes,
                                   void *stream);
 
+/* ----------------------------------------------------------- clustering */
+
+/* Workspace bytes for clusco_kmedoids (0 if invalid): 256 + 8 N rounded up
+ * to a multiple of 256. */
+size_t clusco_cluster_workspace_size(clusco_handle h, int64_t N, int32_t k);
+
+/* K-means clustering of a packed score matrix (Implementation; Results and
+ * Discussion: K-means over the all-vs-all matrix, k clusters, and the
+ * representative chosen by the smallest <R>/f).  Only the N(N-1)/2 scores
+ * are used, so every cluster centre is one of its members (a medoid).
+ * Alternating steps from the caller's k distinct initial medoids:
+ *   assign  every model joins the cluster of its nearest medoid (float32
+ *           comparison; ties to the lowest cluster index; a medoid always
+ *           joins its own cluster);
+ *   update  each cluster's new medoid is the member with the smallest sum of
+ *           scores to the other members (ties to the lowest model index);
+ * until no medoid changes or max_iter updates have run (then one more
+ * assignment).  Each score is rounded once to a multiple of 2^-20 and summed
+ * exactly in 64-bit integers, so results do not depend on summation order.
+ * Scores must be finite, non-negative and below 2^22.
+ *   D       device float32 [N(N-1)/2], the packed matrix of any entry point
+ *   h_init  HOST int32 [k], distinct model indices in [0, N); copied on the
+ *           stream before the call returns
+ *   labels  device int32 [N]: cluster of each model
+ *   medoids device int32 [k]: final medoids
+ *   sizes   device int64 [k]: n_c
+ *   mean_r  device float64 [k]: <R>_c, the mean score over the n_c(n_c-1)/2
+ *           pairs of cluster c (0 when n_c = 1)
+ *   info    device int64 [3]: the representative cluster (smallest
+ *           <R>_c N / n_c over clusters with n_c >= 2; ties to the lowest
+ *           index; -1 if none), updates run, 1 if converged
+ * The representative model is medoids[info[0]].  Every step is enqueued on
+ * the stream without host synchronisation (steps after convergence return
+ * at once).  1 <= k <= N <= 2^20, 0 <= max_iter <= 100000. */
+clusco_status clusco_kmedoids(clusco_handle h, const float *D, int64_t N, int32_t k,
+                              const int32_t *h_init, int32_t max_iter, int32_t *labels,
+                              int32_t *medoids, int64_t *sizes, double *mean_r, int64_t *info,
+                              void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,10 +9,10 @@ from .autograd import CRMSDCross, CRMSDMatrix, crmsd_cross_ad, crmsd_matrix_ad  
 from .binding import (Batch, ClucsoError, PRECISION, batched_workspace_size,  # noqa: F401
                       crmsd_backward, crmsd_batched, crmsd_cross, crmsd_cross_backward,
                       crmsd_matrix, crmsd_threshold, drmsd_matrix, drmsd_workspace_size,
-                      fixup_count, set_tolerance, workspace_size)
+                      fixup_count, kmedoids, set_tolerance, workspace_size)
 
 __all__ = ["Batch", "CRMSDCross", "CRMSDMatrix", "ClucsoError", "PRECISION",
            "batched_workspace_size", "crmsd_backward", "crmsd_batched", "crmsd_cross",
            "crmsd_cross_ad", "crmsd_cross_backward", "crmsd_matrix", "crmsd_matrix_ad",
-           "crmsd_threshold", "drmsd_matrix", "drmsd_workspace_size",
+           "crmsd_threshold", "drmsd_matrix", "drmsd_workspace_size", "kmedoids",
            "fixup_count", "set_tolerance", "workspace_size"]

@@ -58,6 +58,8 @@ def lib():
             "clusco_crmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_drmsd_workspace_size": (sz, [vp, i64, i64, st]),
+            "clusco_cluster_workspace_size": (sz, [vp, i64, i32]),
+            "clusco_kmedoids": (st, [vp, vp, i64, i32, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
             "clusco_drmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_fixup_count": (st, [vp, vp, i64p, vp]),
             "clusco_stage_timing": (st, [vp, ctypes.c_int]),
@@ -189,6 +191,38 @@ def drmsd_matrix(x: torch.Tensor, precision="bf16", out: torch.Tensor | None = N
     rc = lib().clusco_drmsd_matrix(h, _ptr(x), N, L, p, _ptr(out), _ptr(ws), ws.numel(),
                                    _stream(dev))
     _check(rc, h, "clusco_drmsd_matrix")
+    return out
+
+
+def kmedoids(D: torch.Tensor, N: int, k: int, init=None, max_iter: int = 100,
+             ws: torch.Tensor | None = None) -> dict:
+    """K-means with member centres over a packed score matrix D [N(N-1)/2]
+    (float32, on the GPU).  init: k distinct model indices (host sequence;
+    default: evenly spaced models).  Returns device tensors labels [N],
+    medoids [k], sizes [k], mean_r [k] and info [3] (representative cluster,
+    updates run, converged)."""
+    if D.dtype != torch.float32 or not D.is_cuda or not D.is_contiguous():
+        raise TypeError("D must be a contiguous float32 CUDA tensor")
+    if D.numel() != N * (N - 1) // 2:
+        raise ValueError("D must hold N(N-1)/2 scores")
+    if init is None:
+        init = [(c * N) // k for c in range(k)]
+    h_init = (ctypes.c_int32 * k)(*[int(v) for v in init])
+    dev = D.device
+    h = handle(dev.index)
+    need = int(lib().clusco_cluster_workspace_size(h, N, k))
+    if need == 0:
+        raise ClucsoError(ERR_INVALID_ARG, "clusco_cluster_workspace_size", f"N={N} k={k}")
+    ws = _workspace(need, dev, ws)
+    out = {"labels": torch.empty(N, dtype=torch.int32, device=dev),
+           "medoids": torch.empty(k, dtype=torch.int32, device=dev),
+           "sizes": torch.empty(k, dtype=torch.int64, device=dev),
+           "mean_r": torch.empty(k, dtype=torch.float64, device=dev),
+           "info": torch.empty(3, dtype=torch.int64, device=dev)}
+    rc = lib().clusco_kmedoids(h, _ptr(D), N, k, h_init, max_iter, _ptr(out["labels"]),
+                               _ptr(out["medoids"]), _ptr(out["sizes"]), _ptr(out["mean_r"]),
+                               _ptr(out["info"]), _ptr(ws), ws.numel(), _stream(dev))
+    _check(rc, h, "clusco_kmedoids")
     return out
 
 

@@ -1047,4 +1047,57 @@ clusco_status clusco_drmsd_matrix(clusco_handle h, const float *coords, int64_t 
     return CLUSCO_OK;
 }
 
+// ---------------------------------------------------------- clustering
+
+size_t clusco_cluster_workspace_size(clusco_handle h, int64_t N, int32_t k)
+{
+    if (!h || N < 1 || N > MAX_N || k < 1 || k > N) return 0;
+    return 256 + (size_t)round_up(8 * N, 256);
+}
+
+clusco_status clusco_kmedoids(clusco_handle h, const float *D, int64_t N, int32_t k,
+                              const int32_t *h_init, int32_t max_iter, int32_t *labels,
+                              int32_t *medoids, int64_t *sizes, double *mean_r, int64_t *info,
+                              void *ws, size_t ws_bytes, void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (N < 1 || k < 1 || k > N || max_iter < 0 || max_iter > 100000)
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "need 1 <= k <= N and 0 <= max_iter <= 100000");
+    if (N > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
+    if (!h_init) return fail(h, CLUSCO_ERR_INVALID_ARG, "null initial medoids");
+    {
+        std::vector<int32_t> v(h_init, h_init + k);
+        std::sort(v.begin(), v.end());
+        if (v.front() < 0 || v.back() >= N || std::adjacent_find(v.begin(), v.end()) != v.end())
+            return fail(h, CLUSCO_ERR_INVALID_ARG, "initial medoids must be distinct models in [0, N)");
+    }
+    if ((N > 1 && !D) || !labels || !medoids || !sizes || !mean_r || !info)
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "null matrix or output");
+    if (!aligned(D, 4) || !aligned(labels, 4) || !aligned(medoids, 4) || !aligned(sizes, 8) ||
+        !aligned(mean_r, 8) || !aligned(info, 8))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "misaligned matrix or output");
+    const size_t need = clusco_cluster_workspace_size(h, N, k);
+    if (!ws || ws_bytes < need) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(medoids, h_init, sizeof(int32_t) * k, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(h, e, "copy initial medoids");
+    ClusterLaunch a{};
+    a.D = D;
+    a.N = N;
+    a.k = k;
+    a.medoid = medoids;
+    a.label = labels;
+    a.state = (int *)ws;
+    a.cost = (long long *)((char *)ws + 256);
+    a.size = (long long *)sizes;
+    a.mean_r = mean_r;
+    a.info = (long long *)info;
+    e = launch_cluster(a, max_iter, st);
+    return e == hipSuccess ? CLUSCO_OK : hip_fail(h, e, "clustering launch");
+}
+
 } // extern "C"

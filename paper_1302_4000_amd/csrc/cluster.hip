@@ -1,0 +1,260 @@
+// K-means over the packed score matrix with member centres (medoids), and
+// the representative cluster by the smallest <R>/f (Implementation; Results
+// and Discussion: K-means clustering of the similarity matrix and selection
+// of the representative model).
+//
+// Alternating steps from distinct initial medoids, as many as max_iter
+// updates, every step a launch on the caller's stream with no host
+// synchronisation: a device state word records convergence and every later
+// launch returns at once.
+//
+//  km_assign   one thread per model: nearest medoid by exact float32
+//              comparison (ties to the lowest cluster, a medoid joins its own
+//              cluster); clears the model's cost
+//  km_cost     one pass over the packed matrix in 64x64 pair tiles: for every
+//              pair in one cluster, q = rint(score 2^20) is added to both
+//              models' costs; row and column partial sums are combined in LDS
+//              and reach HBM through one 64-bit integer atomic per row and
+//              column of the tile.  Integer sums are exact, so the result does
+//              not depend on the order of the atomics
+//  km_update   one workgroup per cluster: the member of smallest cost (ties to
+//              the lowest index) becomes the medoid; a change is recorded
+//  km_step     closes the iteration (counts it, converged when nothing changed)
+//  km_stats    one workgroup per cluster: size and the exact sum of costs
+//              (twice the in-cluster pair sum), <R> = sum / (n (n - 1))
+//  km_pick     the cluster of smallest <R> N / n among those with a pair
+#include "internal.h"
+
+namespace clusco {
+
+enum { ST_DONE = 0, ST_CHANGED = 1, ST_ITERS = 2, ST_CONVERGED = 3 };
+
+__device__ __forceinline__ float score_at(const float *D, int64_t N, int64_t i, int64_t j)
+{
+    if (i > j) {
+        const int64_t t = i;
+        i = j;
+        j = t;
+    }
+    return D[packed_index(i, j, N)];
+}
+
+__device__ __forceinline__ long long quant(float d)
+{
+    return (long long)rint((double)d * 1048576.0);
+}
+
+// final = 1: the assignment after the last update when max_iter ran out.
+__global__ __launch_bounds__(256) void km_assign(ClusterLaunch a, int final)
+{
+    const int *st = a.state;
+    if (final ? st[ST_CONVERGED] != 0 : st[ST_DONE] != 0) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    int best = -1;
+    for (int c = 0; c < a.k; ++c)
+        if (a.medoid[c] == i) {
+            best = c;
+            break;
+        }
+    if (best < 0) {
+        float bd = 0.0f;
+        for (int c = 0; c < a.k; ++c) {
+            const float d = score_at(a.D, a.N, i, a.medoid[c]);
+            if (best < 0 || d < bd) {
+                best = c;
+                bd = d;
+            }
+        }
+    }
+    a.label[i] = best;
+    a.cost[i] = 0;
+}
+
+constexpr int KT = 64;   // pair tile edge of the cost pass
+
+__global__ __launch_bounds__(256) void km_cost(ClusterLaunch a, int final)
+{
+    const int *st = a.state;
+    if (final ? st[ST_CONVERGED] != 0 : st[ST_DONE] != 0) return;
+    __shared__ unsigned long long rows[KT];
+    __shared__ unsigned long long cols[4][KT];
+    const int64_t nt = (a.N + KT - 1) / KT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, g = tid >> 6;
+    for (int64_t t = blockIdx.x; t < tri_count(nt); t += gridDim.x) {
+        int64_t bi, bj;
+        tri_decode(t, nt, &bi, &bj);
+        if (tid < KT) rows[tid] = 0;
+        __syncthreads();
+        const int64_t j = bj * KT + lane;
+        const int lj = j < a.N ? a.label[j] : -1;
+        unsigned long long cs = 0;
+        for (int r = g * 16; r < g * 16 + 16; ++r) {
+            const int64_t i = bi * KT + r;
+            if (i >= a.N) break;
+            if (i < j && j < a.N && a.label[i] == lj) {
+                const unsigned long long q = (unsigned long long)quant(a.D[packed_index(i, j, a.N)]);
+                cs += q;
+                atomicAdd(&rows[r], q);
+            }
+        }
+        cols[g][lane] = cs;
+        __syncthreads();
+        if (tid < KT) {
+            const unsigned long long c = cols[0][tid] + cols[1][tid] + cols[2][tid] + cols[3][tid];
+            const int64_t jj = bj * KT + tid;
+            if (c != 0) atomicAdd((unsigned long long *)&a.cost[jj], c);
+            const int64_t ii = bi * KT + tid;
+            if (rows[tid] != 0) atomicAdd((unsigned long long *)&a.cost[ii], rows[tid]);
+        }
+        __syncthreads();
+    }
+}
+
+// Block-wide lexicographic minimum of (key, index) over 256 threads.
+__device__ __forceinline__ void block_min(long long &key, int64_t &idx)
+{
+    __shared__ long long sk[256];
+    __shared__ int64_t si[256];
+    const int tid = threadIdx.x;
+    sk[tid] = key;
+    si[tid] = idx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            const long long k2 = sk[tid + s];
+            const int64_t i2 = si[tid + s];
+            if (i2 >= 0 && (si[tid] < 0 || k2 < sk[tid] || (k2 == sk[tid] && i2 < si[tid]))) {
+                sk[tid] = k2;
+                si[tid] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    key = sk[0];
+    idx = si[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void km_update(ClusterLaunch a)
+{
+    if (a.state[ST_DONE] != 0) return;
+    const int c = blockIdx.x;
+    long long key = 0;
+    int64_t idx = -1;
+    for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x)
+        if (a.label[i] == c && (idx < 0 || a.cost[i] < key)) {   // ascending i: ties keep the first
+            key = a.cost[i];
+            idx = i;
+        }
+    block_min(key, idx);
+    if (threadIdx.x == 0 && idx >= 0 && idx != a.medoid[c]) {
+        a.medoid[c] = (int)idx;
+        atomicOr(&a.state[ST_CHANGED], 1);
+    }
+}
+
+__global__ void km_step(ClusterLaunch a)
+{
+    int *st = a.state;
+    if (threadIdx.x != 0 || st[ST_DONE] != 0) return;
+    st[ST_ITERS] += 1;
+    if (st[ST_CHANGED] == 0) {
+        st[ST_DONE] = 1;
+        st[ST_CONVERGED] = 1;
+    }
+    st[ST_CHANGED] = 0;
+}
+
+__global__ void km_clear(ClusterLaunch a)
+{
+    if (threadIdx.x < 4) a.state[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void km_stats(ClusterLaunch a)
+{
+    __shared__ long long sn[256], ss[256];
+    const int c = blockIdx.x;
+    long long n = 0, s = 0;
+    for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x)
+        if (a.label[i] == c) {
+            ++n;
+            s += a.cost[i];
+        }
+    sn[threadIdx.x] = n;
+    ss[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            sn[threadIdx.x] += sn[threadIdx.x + k];
+            ss[threadIdx.x] += ss[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        n = sn[0];
+        a.size[c] = n;
+        a.mean_r[c] = n > 1 ? ((double)ss[0] / 1048576.0) / ((double)n * (double)(n - 1)) : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void km_pick(ClusterLaunch a)
+{
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    double best = 0.0;
+    int bc = -1;
+    for (int c = threadIdx.x; c < a.k; c += blockDim.x) {
+        const long long n = a.size[c];
+        if (n > 1) {
+            const double v = a.mean_r[c] * ((double)a.N / (double)n);
+            if (bc < 0 || v < best) {
+                best = v;
+                bc = c;
+            }
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const int c2 = si[threadIdx.x + s];
+            const double v2 = sv[threadIdx.x + s];
+            if (c2 >= 0 && (si[threadIdx.x] < 0 || v2 < sv[threadIdx.x] ||
+                            (v2 == sv[threadIdx.x] && c2 < si[threadIdx.x]))) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = c2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.info[0] = si[0];
+        a.info[1] = a.state[ST_ITERS];
+        a.info[2] = a.state[ST_CONVERGED];
+    }
+}
+
+hipError_t launch_cluster(const ClusterLaunch &a, int max_iter, hipStream_t s)
+{
+    const dim3 b(256), gn((unsigned)((a.N + 255) / 256)), gk((unsigned)a.k);
+    const int64_t nt = (a.N + KT - 1) / KT;
+    const int64_t tiles = tri_count(nt);
+    const dim3 gc((unsigned)(tiles < 8192 ? tiles : 8192));
+    km_clear<<<1, 64, 0, s>>>(a);
+    for (int it = 0; it < max_iter; ++it) {
+        km_assign<<<gn, b, 0, s>>>(a, 0);
+        km_cost<<<gc, b, 0, s>>>(a, 0);
+        km_update<<<gk, b, 0, s>>>(a);
+        km_step<<<1, 64, 0, s>>>(a);
+    }
+    km_assign<<<gn, b, 0, s>>>(a, 1);
+    km_cost<<<gc, b, 0, s>>>(a, 1);
+    km_stats<<<gk, b, 0, s>>>(a);
+    km_pick<<<1, b, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+} // namespace clusco

@@ -280,6 +280,23 @@ hipError_t launch_dist_prep(int mode, const DistLaunch &a, hipStream_t s);
 hipError_t launch_dist_tile(int mode, const DistLaunch &a, hipStream_t s);
 hipError_t launch_dist_fixup(const DistLaunch &a, hipStream_t s);
 
+// Clustering of a packed score matrix (K-means with member centres).
+struct ClusterLaunch {
+    const float *D;       // packed scores [N(N-1)/2]
+    int64_t N;
+    int32_t k;
+    int32_t pad;
+    int32_t *medoid;      // [k], holds the initial medoids at launch
+    int32_t *label;       // [N]
+    long long *cost;      // [N] exact sums of rounded scores (workspace)
+    int *state;           // [4] done, changed, iterations, converged (workspace)
+    long long *size;      // [k]
+    double *mean_r;       // [k]
+    long long *info;      // [3] representative cluster, iterations, converged
+};
+
+hipError_t launch_cluster(const ClusterLaunch &a, int max_iter, hipStream_t s);
+
 // Workspace of one launch: counters, then per-set regions, then the list.
 struct WsLayout {
     size_t total;

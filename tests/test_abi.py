@@ -188,3 +188,26 @@ def test_drmsd_sizes_and_argument_errors(L, h):
     assert f(h, FAKE, 100, 50, 0, FAKE, ctypes.c_void_p(0x10040), need, None) == \
         binding.ERR_INVALID_ARG
     assert f(h, None, 1, 50, 1, None, None, 0, None) == binding.OK
+
+
+def test_kmedoids_sizes_and_argument_errors(L, h):
+    assert L.clusco_cluster_workspace_size(h, 1000, 20) == 256 + 8192   # 8 N, 256-byte units
+    assert L.clusco_cluster_workspace_size(h, 10, 11) == 0
+    assert L.clusco_cluster_workspace_size(h, 10, 0) == 0
+    f = L.clusco_kmedoids
+    init = (ctypes.c_int32 * 3)(0, 5, 9)
+    need = L.clusco_cluster_workspace_size(h, 10, 3)
+    args = lambda **kw: [kw.get("h", h), kw.get("D", FAKE), kw.get("N", 10), kw.get("k", 3),
+                         kw.get("init", init), kw.get("it", 50), FAKE, FAKE, FAKE, FAKE, FAKE,
+                         kw.get("ws", FAKE), kw.get("wsb", need), None]
+    assert f(*args(h=None)) == binding.ERR_INVALID_ARG
+    assert f(*args(k=11)) == binding.ERR_INVALID_ARG
+    assert f(*args(it=-1)) == binding.ERR_INVALID_ARG
+    assert f(*args(init=None)) == binding.ERR_INVALID_ARG
+    assert f(*args(init=(ctypes.c_int32 * 3)(0, 5, 5))) == binding.ERR_INVALID_ARG   # not distinct
+    assert f(*args(init=(ctypes.c_int32 * 3)(0, 5, 10))) == binding.ERR_INVALID_ARG  # out of range
+    assert b"distinct" in L.clusco_last_error(h)
+    assert f(*args(D=None)) == binding.ERR_INVALID_ARG
+    assert f(*args(D=FAKE_ODD)) == binding.ERR_INVALID_ARG
+    assert f(*args(wsb=need - 1)) == binding.ERR_WORKSPACE
+    assert f(*args(ws=ctypes.c_void_p(0x10040))) == binding.ERR_INVALID_ARG

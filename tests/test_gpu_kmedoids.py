@@ -1,0 +1,112 @@
+"""GPU parity of the clustering of the score matrix (K-means with member
+centres and the min <R>/f representative) against the oracle, on the very
+same float32 matrix: labels, medoids, sizes, iteration count and the
+representative must match exactly (all decisions are exact: float32
+comparisons and integer sums), and <R> bit for bit (the same FP64 formula
+applied to the same integers).  At N=20000 the fixed-point properties are
+checked instead."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_4000_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1302_4000_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def compare(cl, D_np, N, k, init, max_iter=100):
+    D = torch.from_numpy(np.ascontiguousarray(D_np, dtype=np.float32)).cuda()
+    got = cl.kmedoids(D, N, k, init, max_iter)
+    torch.cuda.synchronize()
+    got = {n: t.cpu().numpy() for n, t in got.items()}
+    want = oracle.kmedoids(D_np, N, k, init, max_iter)
+    assert np.array_equal(got["labels"], want["labels"])
+    assert np.array_equal(got["medoids"], want["medoids"])
+    assert np.array_equal(got["sizes"], want["sizes"])
+    assert np.array_equal(got["mean_r"], want["mean_r"])
+    assert got["info"][0] == want["rep_cluster"]
+    assert got["info"][1] == want["iterations"]
+    assert bool(got["info"][2]) == want["converged"]
+    return want
+
+
+def line_matrix(x):
+    x = np.asarray(x, dtype=np.float64)
+    i, j = np.triu_indices(len(x), 1)
+    return np.abs(x[i] - x[j]).astype(np.float32)
+
+
+def test_small_cases_and_ties(cl):
+    say("[kmedoids] tiny cases, ties, k = N, max_iter = 0")
+    compare(cl, line_matrix([0, 1, 2, 3, 50]), 5, 2, [3, 4])
+    compare(cl, line_matrix([0, 5, 10, 100, 15]), 5, 2, [1, 4], max_iter=0)
+    compare(cl, line_matrix([0, 1, 3, 7]), 4, 4, [3, 2, 1, 0])
+    compare(cl, line_matrix([0.0, 2.0]), 2, 1, [1])
+    compare(cl, np.zeros(0, np.float32), 1, 1, [0])
+    compare(cl, np.zeros(45, np.float32), 10, 3, [7, 2, 5])     # all scores equal
+
+
+@pytest.mark.parametrize("N,L,k,seed", [(300, 60, 5, 0), (257, 33, 12, 1), (1000, 100, 20, 2)])
+def test_crmsd_matrix_clusters(cl, N, L, k, seed):
+    say(f"[kmedoids] cRMSD matrix N={N} L={L} k={k}")
+    x = synth.make_ensemble(300 + seed, N, L, sigma=(0.3, 5.0))
+    D = cl.crmsd_matrix(torch.from_numpy(x).cuda(), "bf16").cpu().numpy()
+    init = np.random.default_rng(seed).choice(N, k, replace=False)
+    r = compare(cl, D, N, k, init)
+    say(f"  iterations {r['iterations']} converged {r['converged']} rep {r['rep_cluster']}")
+
+
+def test_n5000_against_oracle(cl):
+    say("[kmedoids] N=5000 L=300 k=20 against the oracle")
+    x = synth.workload("n5000_l300")
+    D = cl.crmsd_matrix(torch.from_numpy(x).cuda(), "bf16").cpu().numpy()
+    r = compare(cl, D, 5000, 20, [(c * 5000) // 20 for c in range(20)])
+    say(f"  iterations {r['iterations']} converged {r['converged']}")
+
+
+def test_n20000_fixed_point(cl):
+    say("[kmedoids] N=20000 L=150 k=20 fixed-point properties")
+    N, k = 20000, 20
+    x = synth.workload("n20000_l150")
+    Dd = cl.crmsd_matrix(torch.from_numpy(x).cuda(), "bf16")
+    init = [(c * N) // k for c in range(k)]
+    got = {n: t.cpu().numpy() for n, t in cl.kmedoids(Dd, N, k, init, 200).items()}
+    lab, med = got["labels"], got["medoids"]
+    assert got["info"][2] == 1 and 1 <= got["info"][1] <= 200
+    assert len(set(med.tolist())) == k and got["sizes"].sum() == N
+    D = Dd.cpu().numpy()
+
+    def score(i, j):
+        i, j = np.minimum(i, j), np.maximum(i, j)
+        return D[oracle.packed_index(i, j, N)].astype(np.float64)
+    idx = np.arange(N)
+    dist = np.stack([np.where(idx == m, 0.0, score(idx, np.full(N, m))) for m in med], 1)
+    want = np.argmin(dist, 1)                       # first minimum = lowest cluster on ties
+    for c, m in enumerate(med):
+        want[m] = c
+    assert np.array_equal(lab, want)
+    for c in range(k):
+        mem = np.flatnonzero(lab == c)
+        cost = np.zeros(len(mem))
+        for s0 in range(0, len(mem), 256):           # in-cluster sums, 256 rows at a time
+            I, J = np.meshgrid(mem[s0:s0 + 256], mem, indexing="ij")
+            q = np.where(I == J, 0.0, np.rint(score(I.ravel(), J.ravel()).reshape(I.shape) * 2.0**20))
+            cost[s0:s0 + 256] = q.sum(1)
+        assert med[c] == mem[int(np.argmin(cost))]
+        n = len(mem)
+        if n > 1:
+            assert got["mean_r"][c] == (cost.sum() / 2.0**20) / (n * (n - 1.0))
+    say(f"  iterations {got['info'][1]}, representative cluster {got['info'][0]}")
