@@ -8,7 +8,8 @@ the definition of cRMSD (Algorithms, Eq. 1) evaluated with an explicit Kabsch
 superposition (one-sided Jacobi SVD of the 3x3 correlation matrix, proper
 rotation, explicit residual), and the definition of dRMSD (Algorithms, Eq. 5)
 as a direct sum over atom pairs.  Every function takes float32 or float64
-coordinates and promotes them exactly to float64.  ``kmedoids`` clusters a
+coordinates and promotes them exactly to float64.  ``cmo*`` give the contact map overlap (Algorithms, Eq. 6-7)
+with integer contact counts.  ``kmedoids`` clusters a
 packed float32 score matrix (K-means with member centres, the representative
 by the smallest <R>/f) with exact integer sums.
 
@@ -67,6 +68,12 @@ def _load():
     lib.oracle_drmsd_pair.argtypes = [dp, dp, i64]
     lib.oracle_drmsd_matrix.argtypes = [dp, i64, i64, dp, cint]
     lib.oracle_drmsd_pairs.argtypes = [dp, i64, i64, lp, lp, i64, dp, cint]
+    lib.oracle_cmo_pair.restype = ctypes.c_double
+    lib.oracle_cmo_pair.argtypes = [dp, dp, i64, ctypes.c_double]
+    lib.oracle_cmo_matrix.argtypes = [dp, i64, i64, ctypes.c_double, dp, cint]
+    lib.oracle_cmo_pairs.argtypes = [dp, i64, i64, ctypes.c_double, lp, lp, i64, dp, cint]
+    lib.oracle_cmo_matrix.restype = cint
+    lib.oracle_cmo_pairs.restype = cint
     i32p = ctypes.POINTER(ctypes.c_int32)
     fp = ctypes.POINTER(ctypes.c_float)
     lib.oracle_kmedoids.argtypes = [fp, i64, i64, i32p, i64, i32p, i32p, lp, dp, lp]
@@ -211,6 +218,34 @@ def drmsd_pairs(x, I, J, threads: int = 0) -> np.ndarray:
     _check(_load().oracle_drmsd_pairs(_p(x), x.shape[0], x.shape[1], I.ctypes.data_as(lp),
                                       J.ctypes.data_as(lp), I.shape[0], _p(out), threads),
            "drmsd_pairs")
+    return out
+
+
+def cmo(A, B, cutoff: float) -> float:
+    """Contact map overlap (Sorensen index, 0..100) of two models."""
+    A, B = _d(A), _d(B)
+    return float(_load().oracle_cmo_pair(_p(A), _p(B), A.shape[0], float(cutoff)))
+
+
+def cmo_matrix(x, cutoff: float, threads: int = 0) -> np.ndarray:
+    """Packed all-vs-all contact map overlap of an [N,L,3] ensemble."""
+    x = _d(x)
+    N, L = x.shape[0], x.shape[1]
+    out = np.zeros(N * (N - 1) // 2)
+    _check(_load().oracle_cmo_matrix(_p(x), N, L, float(cutoff), _p(out), threads), "cmo_matrix")
+    return out
+
+
+def cmo_pairs(x, I, J, cutoff: float, threads: int = 0) -> np.ndarray:
+    """Contact map overlap of selected pairs (I[p], J[p]) of one ensemble."""
+    x = _d(x)
+    I = np.ascontiguousarray(I, dtype=np.int64)
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    out = np.zeros(I.shape[0])
+    lp = ctypes.POINTER(ctypes.c_int64)
+    _check(_load().oracle_cmo_pairs(_p(x), x.shape[0], x.shape[1], float(cutoff),
+                                    I.ctypes.data_as(lp), J.ctypes.data_as(lp), I.shape[0],
+                                    _p(out), threads), "cmo_pairs")
     return out
 
 

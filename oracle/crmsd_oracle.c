@@ -572,3 +572,61 @@ int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, i
     free(cost);
     return 0;
 }
+
+/* -------------------------------------------------------------------- CMO
+ * Contact map overlap (Algorithms, Eq. 6-7): atoms p < q of a model are in
+ * contact when their distance is below the cut-off, C_pq = [|x_p - x_q| <
+ * cutoff]; the score of two models is the Sorensen index of their contact
+ * sets, S = 100 * 2 n(A and B) / (n(A) + n(B)), with n the number of
+ * contacts.  Each contact is decided on d^2 = fma(u, u, fma(v, v, w w)) <
+ * cutoff^2 in FP64 (u, v, w the exact FP64 coordinate differences); the
+ * counts are integers.  S = 0 when neither model has a contact. */
+static int in_contact(const double *X, int64_t p, int64_t q, double c2)
+{
+    const double u = X[3 * p] - X[3 * q];
+    const double v = X[3 * p + 1] - X[3 * q + 1];
+    const double w = X[3 * p + 2] - X[3 * q + 2];
+    return fma(u, u, fma(v, v, w * w)) < c2;
+}
+
+double oracle_cmo_pair(const double *A, const double *B, int64_t L, double cutoff)
+{
+    const double c2 = cutoff * cutoff;
+    int64_t na = 0, nb = 0, nab = 0;
+    for (int64_t p = 0; p < L; ++p)
+        for (int64_t q = p + 1; q < L; ++q) {
+            const int a = in_contact(A, p, q, c2), b = in_contact(B, p, q, c2);
+            na += a;
+            nb += b;
+            nab += a & b;
+        }
+    if (na + nb == 0) return 0.0;
+    return (200.0 * (double)nab) / (double)(na + nb);
+}
+
+int oracle_cmo_matrix(const double *X, int64_t N, int64_t L, double cutoff, double *out,
+                      int nthreads)
+{
+    if (N < 0 || L < 1 || !(cutoff >= 0.0)) return 1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t base = i * (2 * N - i - 1) / 2 - i - 1;
+        for (int64_t j = i + 1; j < N; ++j)
+            out[base + j] = oracle_cmo_pair(X + 3 * L * i, X + 3 * L * j, L, cutoff);
+    }
+    return 0;
+}
+
+int oracle_cmo_pairs(const double *X, int64_t N, int64_t L, double cutoff, const int64_t *I,
+                     const int64_t *J, int64_t P, double *out, int nthreads)
+{
+    if (N < 0 || L < 1 || P < 0 || !(cutoff >= 0.0)) return 1;
+    for (int64_t p = 0; p < P; ++p)
+        if (I[p] < 0 || I[p] >= N || J[p] < 0 || J[p] >= N) return 2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < P; ++p)
+        out[p] = oracle_cmo_pair(X + 3 * L * I[p], X + 3 * L * J[p], L, cutoff);
+    return 0;
+}

@@ -186,3 +186,51 @@ def test_kmedoids_mutant_is_caught(tmp_path, name):
     src = open(SRC).read()
     assert src.count(old) == 1, "mutation site moved; update the test"
     assert kmedoids_pins_fail(tmp_path, name, src.replace(old, new)), f"mutant {name} passed"
+
+
+CMO_MUTANTS = {
+    "non_strict_cutoff": ("return fma(u, u, fma(v, v, w * w)) < c2;",
+                          "return fma(u, u, fma(v, v, w * w)) <= c2;"),
+    "no_factor_two": ("return (200.0 * (double)nab) / (double)(na + nb);",
+                      "return (100.0 * (double)nab) / (double)(na + nb);"),
+    "includes_diagonal": ("for (int64_t q = p + 1; q < L; ++q) {\n            const int a = in_contact",
+                          "for (int64_t q = p; q < L; ++q) {\n            const int a = in_contact"),
+    "cutoff_not_squared": ("const double c2 = cutoff * cutoff;", "const double c2 = cutoff;"),
+    "union_denominator": ("return (200.0 * (double)nab) / (double)(na + nb);",
+                          "return (200.0 * (double)nab) / (double)(na + nb - nab);"),
+}
+
+
+def cmo_pins_fail(tmp_path, name, src):
+    import importlib
+    import oracle as orc_mod
+    so = tmp_path / f"{name}.so"
+    c = tmp_path / f"{name}.c"
+    c.write_text(src)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-o", str(so), str(c), "-lm"], check=True)
+    saved = orc_mod._lib, orc_mod._LIB
+    try:
+        orc_mod._lib, orc_mod._LIB = None, str(so)
+        t = importlib.import_module("test_oracle_cmo")
+        for fn in (t.test_worked_examples, t.test_rigid_motion_reflection_symmetry,
+                   t.test_bruteforce_pdist):
+            try:
+                fn(orc_mod)
+            except (AssertionError, ValueError):
+                return True
+        return False
+    finally:
+        orc_mod._lib, orc_mod._LIB = saved
+
+
+def test_unmodified_cmo_passes(tmp_path):
+    assert not cmo_pins_fail(tmp_path, "orig_c", open(SRC).read())
+
+
+@pytest.mark.parametrize("name", sorted(CMO_MUTANTS))
+def test_cmo_mutant_is_caught(tmp_path, name):
+    old, new = CMO_MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site moved; update the test"
+    assert cmo_pins_fail(tmp_path, name, src.replace(old, new)), f"mutant {name} passed"
