@@ -969,13 +969,13 @@ DistLayout dist_layout(clusco_handle h, int mode, int64_t N, int64_t L)
     DistLayout r{};
     DistLaunch &d = r.d;
     d.N = N;
-    d.Np = round_up(N > 0 ? N : 1, TILE);
+    d.Np = round_up(N > 0 ? N : 1, 256);   // whole 256-model tiles of operands
     d.L = L;
     d.K = L * (L - 1) / 2;
     d.Kp = round_up(d.K > 0 ? d.K : 1, 16);
     d.KB = d.Kp / kblock(mode == MODE_FP64 ? MODE_BF16 : mode);
     d.nref = N < 256 ? N : 256;
-    d.nb = (d.Np + 127) / 128;
+    d.nb = d.Np / 256;
     d.T = tri_count(d.nb);
     d.nrb = d.Np / ROWBLK;
     size_t o = 256;

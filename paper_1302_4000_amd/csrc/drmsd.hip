@@ -12,11 +12,11 @@
 //  dist_prep    e_m rounded to the operand format in the fragment-native
 //               layout of the cRMSD kernels (one plane), E_m from exactly
 //               the operand values (FP64)
-//  dist_tile    symmetric product on MFMA: a 128x128 tile per workgroup,
-//               64x64 per wave (2x2 MFMA blocks), operands straight from
-//               L2 (waves of a workgroup share rows and columns through L1);
-//               epilogue sqrt(max(E_i + E_j - 2G, 0) / K), packed store, and
-//               the fix-up flag as in the cRMSD path
+//  dist_tile    symmetric product on MFMA: a 256x256 tile per 8-wave
+//               workgroup with the operand chunks staged in LDS per K-block
+//               (double-buffered), 64x128 pairs per wave; epilogue
+//               sqrt(max(E_i + E_j - 2G, 0) / K), packed store, and the
+//               fix-up flag as in the cRMSD path
 //  dist_fixup   flagged pairs recomputed from the raw coordinates entirely in
 //               FP64 (distances and their differences, no Gram identity)
 #include "internal.h"
@@ -140,128 +140,139 @@ __device__ __forceinline__ f32x16 mfma16(u32x4 x, u32x4 y, f32x16 c)
 
 __device__ __forceinline__ void pin() { asm volatile("" ::: "memory"); }
 
-constexpr int DT = 128;   // models per workgroup tile edge (2x2 waves of 64)
+constexpr int GT = 256;            // models per workgroup tile edge
+constexpr int GB = GT / ROWBLK;    // 32-model blocks per tile edge
 
+// One 256x256 pair tile per 8-wave workgroup.  Per K-block the workgroup
+// stages the operand chunks of its 8 row blocks and 8 column blocks in LDS
+// (double-buffered; the next K-block's chunks are loaded into registers while
+// the current one is multiplied), and each wave multiplies 2 row blocks by 4
+// column blocks (64 x 128 pairs, eight 32x32 accumulators).  Every chunk
+// reaches the CU once per K-block instead of once per wave that uses it.
 template <int MODE>
-__global__ __launch_bounds__(256, 2) void dist_tile_kernel(DistLaunch a)
+__global__ __launch_bounds__(512, 1) void dist_tile_kernel(DistLaunch a)
 {
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    constexpr int P = is_split(MODE) ? 2 : 1;      // chunk parts (hi, lo)
+    constexpr int NCH = 2 * GB * P;                // chunks per K-block, A then B
+    constexpr int PER = NCH / 8;                   // chunk loads per thread
+    __shared__ u32x4 lds[2][NCH][64];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, in scalars
     const int64_t per_xcd = gridDim.x >> 3;
     const int64_t t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (t >= a.T) return;
+    if (t >= a.T) return;                          // uniform over the workgroup
     int64_t bi, bj;
     band_decode(t, a.nb, 4, &bi, &bj);
     const int wy = w >> 1, wx = w & 1;
-    if (bi == bj && wy > wx) return;
-    const int64_t R0 = 4 * bi + 2 * wy, C0 = 4 * bj + 2 * wx;   // 32-row blocks
-    if (R0 * ROWBLK >= a.N || C0 * ROWBLK >= a.N) return;
+    // on a diagonal tile, waves wholly below the diagonal multiply too (the
+    // workgroup waits for its slowest wave anyway) but store nothing
+    const bool idle = bi == bj && 2 * wy >= 4 * wx + 4;
+    const int64_t KB = a.KB;
+    const u32x4 *ops = (const u32x4 *)(a.ws + a.off_ops);
+    int64_t src[PER];                              // wave's chunk bases (K-block 0)
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int q = w + 8 * m;
+        const int side = q / (GB * P), r = q % (GB * P);
+        const int64_t R = (side ? bj : bi) * GB + r / P;
+        src[m] = (R * KB * P + r % P) * 64;
+    }
+    const u32x4 *opl = ops + lane;
+    u32x4 pre[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) pre[m] = opl[src[m]];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) lds[0][w + 8 * m][lane] = pre[m];
+    __syncthreads();
 
-    f32x16 acc[2][2];
+    f32x16 acc[2][4];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[s][u][r] = 0.0f;
-    const int64_t KB = a.KB;
-    if constexpr (MODE == MODE_FP32) {
-        const f32x4 *ops = (const f32x4 *)(a.ws + a.off_ops);
-        f32x4 A[2], B[2];
+
+    for (int64_t kb = 0; kb < KB; ++kb) {
+        const int buf = (int)(kb & 1);
+        const bool more = kb + 1 < KB;
+        if (more) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            A[s] = ops[((R0 + s) * KB) * 64 + lane];
-            B[s] = ops[((C0 + s) * KB) * 64 + lane];
+            for (int m = 0; m < PER; ++m) pre[m] = opl[src[m] + (kb + 1) * P * 64];
         }
-        for (int64_t kb = 0; kb < KB; ++kb) {
-            const int64_t nx = kb + 1 < KB ? kb + 1 : kb;
-            f32x4 An[2], Bn[2];
+        pin();
+        {
+            if constexpr (MODE == MODE_FP32) {
+                f32x4 A[2], B[4];
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                An[s] = ops[((R0 + s) * KB + nx) * 64 + lane];
-                Bn[s] = ops[((C0 + s) * KB + nx) * 64 + lane];
-            }
-            pin();
+                for (int s = 0; s < 2; ++s) A[s] = __builtin_bit_cast(f32x4, lds[buf][2 * wy + s][lane]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+                for (int u = 0; u < 4; ++u) B[u] = __builtin_bit_cast(f32x4, lds[buf][GB + 4 * wx + u][lane]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            acc[s][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s][e], B[u][e],
+                                                                            acc[s][u], 0, 0, 0);
+            } else {
+                u32x4 Ah[2], Al[2], Bh[4], Bl[4];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    Ah[s] = lds[buf][(2 * wy + s) * 2][lane];
+                    Al[s] = lds[buf][(2 * wy + s) * 2 + 1][lane];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    Bh[u] = lds[buf][2 * GB + (4 * wx + u) * 2][lane];
+                    Bl[u] = lds[buf][2 * GB + (4 * wx + u) * 2 + 1][lane];
+                }
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int u = 0; u < 2; ++u)
-                        acc[s][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s][e], B[u][e],
-                                                                        acc[s][u], 0, 0, 0);
-            pin();
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                A[s] = An[s];
-                B[s] = Bn[s];
-            }
-        }
-    } else {
-        // chunk (R, kb, part) at ((R*KB + kb)*2 + part) * 64 lanes
-        const u32x4 *ops = (const u32x4 *)(a.ws + a.off_ops);
-        u32x4 Ah[2], Al[2], Bh[2], Bl[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            Ah[s] = ops[(((R0 + s) * KB) * 2) * 64 + lane];
-            Al[s] = ops[(((R0 + s) * KB) * 2 + 1) * 64 + lane];
-            Bh[s] = ops[(((C0 + s) * KB) * 2) * 64 + lane];
-            Bl[s] = ops[(((C0 + s) * KB) * 2 + 1) * 64 + lane];
-        }
-        for (int64_t kb = 0; kb < KB; ++kb) {
-            const int64_t nx = kb + 1 < KB ? kb + 1 : kb;
-            u32x4 Ahn[2], Aln[2], Bhn[2], Bln[2];
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                Ahn[s] = ops[(((R0 + s) * KB + nx) * 2) * 64 + lane];
-                Aln[s] = ops[(((R0 + s) * KB + nx) * 2 + 1) * 64 + lane];
-                Bhn[s] = ops[(((C0 + s) * KB + nx) * 2) * 64 + lane];
-                Bln[s] = ops[(((C0 + s) * KB + nx) * 2 + 1) * 64 + lane];
-            }
-            pin();
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) acc[s][u] = mfma16<MODE>(Ah[s], Bh[u], acc[s][u]);
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) acc[s][u] = mfma16<MODE>(Ah[s], Bl[u], acc[s][u]);
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) acc[s][u] = mfma16<MODE>(Al[s], Bh[u], acc[s][u]);
-            if constexpr (MODE == MODE_BF16X4) {
+                    for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Ah[s], Bh[u], acc[s][u]);
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) acc[s][u] = mfma16<MODE>(Al[s], Bl[u], acc[s][u]);
-            }
-            pin();
+                    for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Ah[s], Bl[u], acc[s][u]);
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                Ah[s] = Ahn[s];
-                Al[s] = Aln[s];
-                Bh[s] = Bhn[s];
-                Bl[s] = Bln[s];
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Al[s], Bh[u], acc[s][u]);
+                if constexpr (MODE == MODE_BF16X4) {
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Al[s], Bl[u], acc[s][u]);
+                }
             }
         }
+        if (more) {
+#pragma unroll
+            for (int m = 0; m < PER; ++m) lds[buf ^ 1][w + 8 * m][lane] = pre[m];
+        }
+        __syncthreads();
     }
+    if (idle) return;
 
     // epilogue: lane holds column j = lane%32, rows 8(r/4) + 4(lane/32) + r%4
     const double *E = (const double *)(a.ws + a.off_E);
     const int64_t N = a.N;
     const double invK = 1.0 / (double)a.K;
-    bool flagged[2][2] = {{false, false}, {false, false}};
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int64_t j = (C0 + u) * ROWBLK + (lane & 31);
+    for (int u = 0; u < 4; ++u) {
+        const int64_t C = bj * GB + 4 * wx + u;
+        const int64_t j = C * ROWBLK + (lane & 31);
         const double Ej = E[j];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
+            const int64_t R = bi * GB + 2 * wy + s;
+            bool flagged = false;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int64_t i0 = (R0 + s) * ROWBLK + 8 * g + 4 * (lane >> 5);
+                const int64_t i0 = R * ROWBLK + 8 * g + 4 * (lane >> 5);
                 int64_t base = i0 * (2 * N - i0 - 1) / 2 - i0 - 1;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -271,20 +282,16 @@ __global__ __launch_bounds__(256, 2) void dist_tile_kernel(DistLaunch a)
                     const float v = sqrtf((float)fmax(r2, 0.0));
                     const bool live = i < j && j < N;
                     if (live) a.out[base + j] = v;
-                    flagged[s][u] |= live && (double)v < a.flag_coef * (Ei + Ej);
+                    flagged |= live && (double)v < a.flag_coef * (Ei + Ej);
                     base += N - i - 2;
                 }
             }
+            if (__any(flagged) && lane == 0) {
+                const int k = atomicAdd(&a.counters[0], 1);
+                a.list[k] = FixEntry{0u, ((uint32_t)R << 16) | (uint32_t)C};
+            }
         }
     }
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (__any(flagged[s][u]) && lane == 0) {
-                const int k = atomicAdd(&a.counters[0], 1);
-                a.list[k] = FixEntry{0u, ((uint32_t)(R0 + s) << 16) | (uint32_t)(C0 + u)};
-            }
 }
 
 // FP64 recomputation of flagged pairs straight from the definition.
@@ -351,7 +358,7 @@ hipError_t launch_dist_prep(int mode, const DistLaunch &a, hipStream_t s)
 
 hipError_t launch_dist_tile(int mode, const DistLaunch &a, hipStream_t s)
 {
-    const dim3 tg((unsigned)round_up(a.T, 8)), tb(256);
+    const dim3 tg((unsigned)round_up(a.T, 8)), tb(512);
     switch (mode) {
     case MODE_FP32: dist_tile_kernel<MODE_FP32><<<tg, tb, 0, s>>>(a); break;
     case MODE_BF16: dist_tile_kernel<MODE_BF16><<<tg, tb, 0, s>>>(a); break;

@@ -116,6 +116,53 @@ __device__ __forceinline__ double eq2_lrmsd2(const double h[9], double EA, doubl
     return fma(-2.0, eq2_signed_sum(h), EA + EB);
 }
 
+// L * cRMSD^2 of NP independent pairs at once.  The same arithmetic as
+// eq2_lrmsd2 with the NP dependency chains written side by side, so that one
+// wave's instruction stream alternates between independent pairs and hides
+// the FP64 latency that a single Newton chain exposes.  STEPS Newton steps
+// (then the same rare-lane continuation).
+template <int NP, int STEPS>
+__device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const double (&ea)[NP],
+                                                 const double (&eb)[NP], double (&out)[NP])
+{
+    double c2[NP], c1[NP], c0[NP], det[NP], l[NP], step[NP];
+    bool zero[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const Eq2Coef c = eq2_coefficients(h[p]);
+        const bool pos = c.c2 > 0.0;
+        zero[p] = !pos;                            // H = 0: the sum is 0, the score E_A + E_B
+        c2[p] = pos ? c.c2 : 1.0;
+        c1[p] = pos ? c.c1 : 0.0;
+        det[p] = pos ? c.det : 0.0;
+        c0[p] = det[p] * det[p];
+        l[p] = fma(-c1[p], __builtin_amdgcn_rcp(c2[p]), c2[p]);
+        step[p] = 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < STEPS; ++it)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) step[p] = eq2_newton(l[p], c2[p], c1[p], c0[p]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (fabs(step[p]) > 1e-9 * l[p]) {
+            for (int it = 0; it < 60 && fabs(step[p]) > 1e-15 * l[p]; ++it)
+                step[p] = eq2_newton(l[p], c2[p], c1[p], c0[p]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const double l1 = fmax(l[p], c2[p] * (1.0 / 3.0));
+        const double r1 = rsqrt_refined(l1);
+        const double s1 = l1 * r1;
+        const double t = fma(2.0 * det[p], r1, c2[p] - l1);
+        const double tp = fmax(t, 1e-300);
+        const double s23 = (t > 0.0) ? tp * rsqrt_refined(tp) : 0.0;
+        const double sum = zero[p] ? 0.0 : s1 + s23;
+        out[p] = fma(-2.0, sum, ea[p] + eb[p]);
+    }
+}
+
 // ------------------------------------------------------------ backward
 
 // Unit vector spanning the null space of the symmetric 3x3 matrix M (given

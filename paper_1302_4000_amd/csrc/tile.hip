@@ -148,6 +148,16 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
     }
 }
 
+// Forward epilogue: pairs evaluated side by side, and Newton steps on the
+// largest root (three take the upper-bound start to ~1e-10 relative on
+// protein-like models; lanes still moving continue as in eq2_largest_root).
+#ifndef EPI_NP
+#define EPI_NP 2
+#endif
+#ifndef EPI_STEPS
+#define EPI_STEPS 4
+#endif
+
 // Tile rows per band of the launch order: 8 x 8 tiles in flight per XCD touch
 // about 2 MB of operands, well inside its 4 MB L2.
 constexpr int64_t BAND = 8;
@@ -217,19 +227,27 @@ __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
         // row base k(i, j) - j: packed rows advance by N - i - 2, dense by NB
         int64_t base = p.sym ? i0 * (2 * NA - i0 - 1) / 2 - i0 - 1 : i0 * NB;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = 4 * g + q;
-            const int64_t i = i0 + q;
-            double h[9];
+        for (int q0 = 0; q0 < 4; q0 += EPI_NP) {
+            double h[EPI_NP][9], ei[EPI_NP], ej[EPI_NP], lr2[EPI_NP];
 #pragma unroll
-            for (int u = 0; u < 9; ++u) h[u] = (double)acc[u][r];
-            const double Ei = EA[i];
-            const double lr2 = eq2_lrmsd2(h, Ei, Ej);
-            const float v = sqrtf((float)fmax(lr2 * invL, 0.0));
-            const bool live = jlive && (p.sym ? i < j : i < NA);
-            if (live) out[base + j] = v;
-            flagged |= live && (double)v < coef * (Ei + Ej);
-            base += p.sym ? NA - i - 2 : NB;
+            for (int b = 0; b < EPI_NP; ++b) {
+#pragma unroll
+                for (int u = 0; u < 9; ++u) h[b][u] = (double)acc[u][4 * g + q0 + b];
+                ei[b] = EA[i0 + q0 + b];
+                ej[b] = Ej;
+            }
+            eq2_lrmsd2_batch<EPI_NP, EPI_STEPS>(h, ei, ej, lr2);
+#pragma unroll
+            for (int b = 0; b < EPI_NP; ++b) {
+                const int64_t i = i0 + q0 + b;
+                // hardware square root (within 1 ulp): the score's tolerance is
+                // orders of magnitude above float rounding
+                const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[b] * invL, 0.0));
+                const bool live = jlive && (p.sym ? i < j : i < NA);
+                if (live) out[base + j] = v;
+                flagged |= live && (double)v < coef * (ei[b] + Ej);
+                base += p.sym ? NA - i - 2 : NB;
+            }
         }
     }
     if (__any(flagged) && lane == 0) {
@@ -317,7 +335,7 @@ __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem 
 #pragma unroll
         for (int u = 0; u < 9; ++u) h[u] = (double)acc[u][r];
         const double Ei = EA[i];
-        const float v = sqrtf((float)fmax(eq2_lrmsd2(h, Ei, Ej) * invL, 0.0));
+        const float v = __builtin_amdgcn_sqrtf((float)fmax(eq2_lrmsd2(h, Ei, Ej) * invL, 0.0));
         const bool live = jlive && i < j;
         const bool fl = live && (double)v < coef * (Ei + Ej);
         vs[r] = v;
@@ -430,6 +448,163 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
     }
 }
 
+// ------------------------------------------------------ staged forward
+//
+// Forward pass of one problem (TK_SYM or TK_RECT): one 64x64 tile per 4-wave
+// workgroup, two workgroups per CU.  The operand chunks of the tile's two
+// row blocks of A and two of B for one K-block (24 KiB in the split modes)
+// are staged in a 3-slot LDS ring: each chunk reaches the CU once instead of
+// once per wave that reads it, and loads run two K-blocks ahead.  Each wave
+// then runs the FP64 epilogue of its 32x32 block.  The two workgroups of a
+// CU are independent, so one's MFMA contraction overlaps the other's FP64
+// epilogue.
+
+constexpr int RING = 3;
+
+template <int MODE>
+struct StageGeom {
+    static constexpr int P = is_split(MODE) ? 2 : 1;   // chunk parts (hi, lo)
+    static constexpr int REGION = 3 * P * 64;           // u32x4 per (row block, K-block)
+    static constexpr int SLOT = 4 * REGION;             // rows 0, 1 of A, rows 0, 1 of B
+    static constexpr int PER = SLOT / 256;              // u32x4 loads per thread
+};
+
+// Thread tid's PER u32x4 of K-block kb of the tile whose first row blocks of
+// A and B are rA and rB (row block R, K-block kb: chunk base (R*KB + kb)*REGION).
+template <int MODE>
+__device__ __forceinline__ void stage_load(const Problem &p, const char *ws, int64_t rA,
+                                           int64_t rB, int64_t kb, int tid,
+                                           u32x4 (&pre)[StageGeom<MODE>::PER])
+{
+    using G = StageGeom<MODE>;
+    const int64_t KB = p.KB;
+    const u32x4 *rowA = (const u32x4 *)(ws + p.opsA) + (rA * KB + kb) * G::REGION;
+    const u32x4 *rowB = (const u32x4 *)(ws + p.opsB) + (rB * KB + kb) * G::REGION;
+    const int64_t next = KB * G::REGION;            // the next row block, same K-block
+#pragma unroll
+    for (int m = 0; m < G::PER; ++m) {
+        const int q = tid + 256 * m;
+        const int region = q / G::REGION, off = q % G::REGION;
+        const u32x4 *base = region < 2 ? rowA : rowB;
+        pre[m] = base[(region & 1) * next + off];
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void stage_store(u32x4 *slot, int tid,
+                                            const u32x4 (&pre)[StageGeom<MODE>::PER])
+{
+#pragma unroll
+    for (int m = 0; m < StageGeom<MODE>::PER; ++m) slot[tid + 256 * m] = pre[m];
+}
+
+template <int MODE, int KIND>
+__global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
+{
+    using G = StageGeom<MODE>;
+    __shared__ u32x4 ring[RING][G::SLOT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wy = w >> 1, wx = w & 1;
+    // tiles in banded order, one contiguous chunk per XCD (workgroups are
+    // dealt to the XCDs round-robin)
+    const int64_t per_xcd = gridDim.x >> 3;
+    const int64_t t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (t >= a.T) return;                          // uniform over the workgroup
+    const Problem &p = a.prob;
+    int64_t bi, bj;
+    if constexpr (KIND == TK_SYM) band_decode(t, p.nbA, BAND, &bi, &bj);
+    else band_decode_rect(t, p.nbA, p.nbB, BAND, &bi, &bj);
+    const int64_t KB = p.KB;
+
+    {
+        u32x4 pre[G::PER];
+        stage_load<MODE>(p, a.ws, 2 * bi, 2 * bj, 0, tid, pre);
+        stage_store<MODE>(ring[0], tid, pre);
+        if (KB > 1) {
+            stage_load<MODE>(p, a.ws, 2 * bi, 2 * bj, 1, tid, pre);
+            stage_store<MODE>(ring[1], tid, pre);
+        }
+    }
+    __syncthreads();
+
+    f32x16 acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    for (int64_t kb = 0; kb < KB; ++kb) {
+        const bool more = kb + 2 < KB;
+        u32x4 pre[G::PER];
+        if (more) stage_load<MODE>(p, a.ws, 2 * bi, 2 * bj, kb + 2, tid, pre);
+        pin_order();
+        const u32x4 *sA = &ring[kb % RING][wy * G::REGION + lane];
+        const u32x4 *sB = &ring[kb % RING][(2 + wx) * G::REGION + lane];
+        if constexpr (MODE == MODE_FP32) {
+            f32x4 A[3], B[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                A[c] = __builtin_bit_cast(f32x4, sA[c * 64]);
+                B[c] = __builtin_bit_cast(f32x4, sB[c * 64]);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        acc[3 * c + d] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[c][e], B[d][e],
+                                                                             acc[3 * c + d], 0, 0, 0);
+        } else {
+            // hi*hi', hi*lo', (lo*lo'), lo*hi': the order of the contraction
+            // in the other kernels, so every path rounds identically; at most
+            // three of the four operand sets are live at once
+            u32x4 Ah[3], Bh[3], Al[3], Bl[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Ah[c] = sA[(2 * c) * 64];
+                Bh[c] = sB[(2 * c) * 64];
+                Bl[c] = sB[(2 * c + 1) * 64];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bh[d], acc[3 * c + d]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Al[c] = sA[(2 * c + 1) * 64];
+            if constexpr (MODE == MODE_BF16X4) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        acc[3 * c + d] = mfma_split<MODE>(Al[c], Bl[d], acc[3 * c + d]);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    acc[3 * c + d] = mfma_split<MODE>(Al[c], Bh[d], acc[3 * c + d]);
+        }
+        pin_order();
+        if (more) stage_store<MODE>(ring[(kb + 2) % RING], tid, pre);
+        __syncthreads();
+    }
+
+    WaveJob job;
+    job.Ra = 2 * bi + wy;
+    job.Rb = 2 * bj + wx;
+    job.pidx = 0;
+    job.active = !(p.sym && bi == bj && wy > wx) && job.Ra * ROWBLK < p.NA &&
+                 job.Rb * ROWBLK < p.NB;
+    if (job.active) epilogue(a, p, job, lane, acc);
+}
+
 template <int MODE>
 static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, int op)
 {
@@ -446,8 +621,13 @@ static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, 
         return hipGetLastError();
     }
     switch (a.kind) {
-    case TK_SYM: tile_kernel<MODE, TK_SYM, OP_FWD><<<g, b, 0, s>>>(a); break;
-    case TK_RECT: tile_kernel<MODE, TK_RECT, OP_FWD><<<g, b, 0, s>>>(a); break;
+    case TK_SYM:
+    case TK_RECT: {
+        const dim3 sg((unsigned)round_up(a.T > 0 ? a.T : 1, 8)), sb(256);
+        if (a.kind == TK_SYM) staged_kernel<MODE, TK_SYM><<<sg, sb, 0, s>>>(a);
+        else staged_kernel<MODE, TK_RECT><<<sg, sb, 0, s>>>(a);
+        break;
+    }
     default: tile_kernel<MODE, TK_BATCH, OP_FWD><<<g, b, 0, s>>>(a); break;
     }
     return hipGetLastError();
