@@ -116,33 +116,41 @@ __device__ __forceinline__ double eq2_lrmsd2(const double h[9], double EA, doubl
     return fma(-2.0, eq2_signed_sum(h), EA + EB);
 }
 
-// L * cRMSD^2 of NP independent pairs at once.  The same arithmetic as
-// eq2_lrmsd2 with the NP dependency chains written side by side, so that one
-// wave's instruction stream alternates between independent pairs and hides
-// the FP64 latency that a single Newton chain exposes.  STEPS Newton steps
-// (then the same rare-lane continuation).
+// L * cRMSD^2 of NP independent pairs at once, for the tile epilogue: the
+// arithmetic of eq2_lrmsd2 written with the fewest instructions.  The NP
+// dependency chains sit side by side.  Instead of branches and selects on
+// degenerate inputs, three floors keep every operation finite: the slope in
+// the Newton step (at least 1e-30 c2^2, so a step at an exact double root is
+// 0/tiny = 0), the root (at least c2/3 and 1e-300, so 1/sqrt never sees 0)
+// and (s2 + S s3)^2 (at least 1e-300).  For H = 0 the sum then comes out as
+// about 1e-150 instead of 0, far below the score's resolution.
 template <int NP, int STEPS>
 __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const double (&ea)[NP],
                                                  const double (&eb)[NP], double (&out)[NP])
 {
-    double c2[NP], c1[NP], c0[NP], det[NP], l[NP], step[NP];
-    bool zero[NP];
+    double c2[NP], c1[NP], c0[NP], det[NP], l[NP], step[NP], m2c2[NP], floor_fp[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const Eq2Coef c = eq2_coefficients(h[p]);
-        const bool pos = c.c2 > 0.0;
-        zero[p] = !pos;                            // H = 0: the sum is 0, the score E_A + E_B
-        c2[p] = pos ? c.c2 : 1.0;
-        c1[p] = pos ? c.c1 : 0.0;
-        det[p] = pos ? c.det : 0.0;
-        c0[p] = det[p] * det[p];
-        l[p] = fma(-c1[p], __builtin_amdgcn_rcp(c2[p]), c2[p]);
+        c2[p] = c.c2;
+        c1[p] = c.c1;
+        det[p] = c.det;
+        c0[p] = c.det * c.det;
+        m2c2[p] = -2.0 * c.c2;
+        floor_fp[p] = fmax(1e-30 * (c.c2 * c.c2), 1e-300);
+        l[p] = fma(-c.c1, __builtin_amdgcn_rcp(fmax(c.c2, 1e-300)), c.c2);
         step[p] = 0.0;
     }
 #pragma unroll
-    for (int it = 0; it < STEPS; ++it)
+    for (int it = 0; it < STEPS; ++it) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) step[p] = eq2_newton(l[p], c2[p], c1[p], c0[p]);
+        for (int p = 0; p < NP; ++p) {
+            const double f = fma(fma(l[p] - c2[p], l[p], c1[p]), l[p], -c0[p]);
+            const double fp = fma(fma(3.0, l[p], m2c2[p]), l[p], c1[p]);
+            step[p] = f * __builtin_amdgcn_rcp(fmax(fp, floor_fp[p]));
+            l[p] -= step[p];
+        }
+    }
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         if (fabs(step[p]) > 1e-9 * l[p]) {
@@ -152,13 +160,11 @@ __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const
     }
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const double l1 = fmax(l[p], c2[p] * (1.0 / 3.0));
+        const double l1 = fmax(l[p], fmax(c2[p] * (1.0 / 3.0), 1e-300));
         const double r1 = rsqrt_refined(l1);
-        const double s1 = l1 * r1;
-        const double t = fma(2.0 * det[p], r1, c2[p] - l1);
+        const double t = fma(2.0 * det[p], r1, c2[p] - l1);        // (s2 + S s3)^2
         const double tp = fmax(t, 1e-300);
-        const double s23 = (t > 0.0) ? tp * rsqrt_refined(tp) : 0.0;
-        const double sum = zero[p] ? 0.0 : s1 + s23;
+        const double sum = fma(l1, r1, tp * rsqrt_refined(tp));    // s1 + s2 + S s3
         out[p] = fma(-2.0, sum, ea[p] + eb[p]);
     }
 }

@@ -148,11 +148,12 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
     }
 }
 
-// Forward epilogue: pairs evaluated side by side, and Newton steps on the
-// largest root (three take the upper-bound start to ~1e-10 relative on
-// protein-like models; lanes still moving continue as in eq2_largest_root).
+// Forward epilogue: EPI_NP pairs evaluated side by side (one measured
+// fastest: a wave's FP64 issue rate, not its dependency chains, is the
+// limit) and EPI_STEPS Newton steps on the largest root before the
+// rare-lane continuation of eq2_largest_root.
 #ifndef EPI_NP
-#define EPI_NP 2
+#define EPI_NP 1
 #endif
 #ifndef EPI_STEPS
 #define EPI_STEPS 4
