@@ -34,7 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = ("all-vs-all cRMSD pairs/s (N=20k,L=150); MFMA util; max err vs FP64 oracle (Å)")
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x4": 2500.0, "fp64": 78.6}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x4": 2500.0, "fp64": 78.6,
+               "int8": 5000.0}
 HBM_PEAK_GBS = 8000.0
 EPI_FLOPS = 146.0   # FP64 flops per pair of the Eq. 2 epilogue as written
 KBLOCK = {"fp32": 8, "bf16": 16, "fp16": 16, "bf16x4": 16, "fp64": 1}
@@ -271,6 +272,47 @@ def drmsd_leg(cl, torch, x, x_np, steps, with_error):
     return res
 
 
+def cmo_leg(cl, torch, x, x_np, steps, with_error):
+    """All-vs-all contact map overlap (Eq. 6-7, cut-off 8 A): an int8 Gram
+    product of 0/1 contact vectors over K = L(L-1)/2 atom pairs.  Algorithmic
+    work 2 K integer operations per pair against the int8 MFMA peak."""
+    import numpy as np
+    N, L = x.shape[0], x.shape[1]
+    P = N * (N - 1) // 2
+    K = L * (L - 1) // 2
+    out = torch.empty(P, dtype=torch.float32, device=x.device)
+    ws = torch.empty(cl.cmo_workspace_size(N, L), dtype=torch.uint8, device=x.device)
+    cl.cmo_matrix(x, 8.0, out=out, ws=ws)
+    torch.cuda.synchronize()
+    dev = x.device.index
+    cl.binding.stage_timing(dev, steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cl.cmo_matrix(x, 8.0, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st, n = cl.binding.stage_times(dev)
+    cl.binding.stage_timing(dev, 0)
+    assert n == steps
+    kern_ms = st[1] / steps
+    ops = 2.0 * K * P
+    r = {"K": K, "cutoff_A": 8.0, "ms_per_call": ms, "pairs_per_s": P / (ms * 1e-3),
+         "kernels_ms": kern_ms, "int8_tops": ops / (kern_ms * 1e-3) / 1e12,
+         "frac_of_int8_peak": ops / (kern_ms * 1e-3) / (PEAK_TFLOPS["int8"] * 1e12)}
+    if with_error:
+        import oracle
+        rng = np.random.default_rng(13)
+        i = rng.integers(0, N, 5000)
+        j = rng.integers(0, N, 5000)
+        k = i != j
+        I, J = np.minimum(i, j)[k], np.maximum(i, j)[k]
+        got = out[torch.from_numpy(oracle.packed_index(I, J, N)).to(x.device)].cpu().numpy()
+        want = oracle.cmo_pairs(x_np, I, J, 8.0).astype(np.float32)
+        r["exact_matches"] = f"{int((got == want).sum())}/{len(I)}"
+    del out, ws
+    return r
+
+
 def kmedoids_leg(cl, torch, D, N, steps):
     """K-means with member centres (k = 20, the paper's setting for decoy
     sets) over the packed matrix the main path produced.  Each update pass
@@ -379,6 +421,9 @@ def main():
         log("[bench] K-means (member centres) on the packed matrix")
         extra["kmedoids"] = kmedoids_leg(cl, torch, main_out, N, max(3, args.steps // 3))
         log(f"[bench] kmedoids: {extra['kmedoids']}")
+        log("[bench] contact map overlap all-vs-all")
+        extra["cmo"] = cmo_leg(cl, torch, x, x_np, max(3, args.steps // 3), not args.no_error)
+        log(f"[bench] cmo: {extra['cmo']}")
         log("[bench] dRMSD all-vs-all")
         extra["drmsd"] = drmsd_leg(cl, torch, x, x_np, max(3, args.steps // 3), not args.no_error)
         log(f"[bench] drmsd: {extra['drmsd']}")

@@ -220,6 +220,28 @@ clusco_status clusco_drmsd_matrix(clusco_handle h, const float *coords, int64_t 
                                   clusco_precision p, float *out, void *ws, size_t ws_bytes,
                                   void *stream);
 
+/* ------------------------------------------------------------------ CMO */
+
+/* Workspace bytes for clusco_cmo_matrix (0 if invalid): about
+ * N * L(L-1)/2 bytes of contact bits plus small tables. */
+size_t clusco_cmo_workspace_size(clusco_handle h, int64_t N, int64_t L);
+
+/* All-vs-all contact map overlap (Algorithms, Eq. 6-7).  Atoms p < q of a
+ * model are in contact when their distance is below `cutoff` (A; the paper
+ * does not state its value), decided on d^2 < cutoff^2 in FP64 from the
+ * float32 coordinates; the score of a pair is the Sorensen index of the two
+ * contact sets,
+ *     S = 100 * 2 n(A and B) / (n(A) + n(B))    in [0, 100],
+ * and 0 when neither model has a contact.  The counts are exact integers
+ * (an int8 Gram product on MFMA); S is their quotient rounded once to
+ * float32.  Higher is more similar.  Same layouts, packed output order,
+ * workspace and stream rules as clusco_crmsd_matrix; no precision choice.
+ * N in {0, 1} returns CLUSCO_OK with nothing enqueued; L = 1 gives zeros;
+ * L above 4096 returns CLUSCO_ERR_UNSUPPORTED; a negative or non-finite
+ * cutoff CLUSCO_ERR_INVALID_ARG. */
+clusco_status clusco_cmo_matrix(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                float cutoff, float *out, void *ws, size_t ws_bytes, void *stream);
+
 /* ----------------------------------------------------------- clustering */
 
 /* Workspace bytes for clusco_kmedoids (0 if invalid): 256 + 8 N rounded up

@@ -59,6 +59,8 @@ def lib():
             "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_drmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_cluster_workspace_size": (sz, [vp, i64, i32]),
+            "clusco_cmo_workspace_size": (sz, [vp, i64, i64]),
+            "clusco_cmo_matrix": (st, [vp, vp, i64, i64, ctypes.c_float, vp, vp, sz, vp]),
             "clusco_kmedoids": (st, [vp, vp, i64, i32, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
             "clusco_drmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_fixup_count": (st, [vp, vp, i64p, vp]),
@@ -191,6 +193,33 @@ def drmsd_matrix(x: torch.Tensor, precision="bf16", out: torch.Tensor | None = N
     rc = lib().clusco_drmsd_matrix(h, _ptr(x), N, L, p, _ptr(out), _ptr(ws), ws.numel(),
                                    _stream(dev))
     _check(rc, h, "clusco_drmsd_matrix")
+    return out
+
+
+def cmo_workspace_size(N: int, L: int, device: int = 0) -> int:
+    return int(lib().clusco_cmo_workspace_size(handle(device), N, L))
+
+
+def cmo_matrix(x: torch.Tensor, cutoff: float = 8.0, out: torch.Tensor | None = None,
+               ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Packed all-vs-all contact map overlap [N(N-1)/2] (Sorensen index, 0..100)
+    of x [N, L, 3] (float32, on the GPU), contacts below `cutoff` Angstrom."""
+    x = _coords(x)
+    N, L = x.shape[0], x.shape[1]
+    dev = x.device
+    h = handle(dev.index)
+    need = int(lib().clusco_cmo_workspace_size(h, N, L))
+    if need == 0:
+        raise ClucsoError(ERR_INVALID_ARG, "clusco_cmo_workspace_size", f"N={N} L={L}")
+    ws = _workspace(need, dev, ws)
+    P = N * (N - 1) // 2
+    if out is None:
+        out = torch.empty(P, dtype=torch.float32, device=dev)
+    elif out.numel() != P or out.dtype != torch.float32 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float32 tensor of N(N-1)/2 elements")
+    rc = lib().clusco_cmo_matrix(h, _ptr(x), N, L, float(cutoff), _ptr(out), _ptr(ws),
+                                 ws.numel(), _stream(dev))
+    _check(rc, h, "clusco_cmo_matrix")
     return out
 
 

@@ -828,7 +828,7 @@ struct ThrLayout {
     size_t off_masks, total;
 };
 
-ThrLayout thr_layout(clusco_handle h, int mode, int64_t N, int64_t L)
+static ThrLayout thr_layout(clusco_handle h, int mode, int64_t N, int64_t L)
 {
     ThrLayout t{};
     t.s = single_layout(h, mode, N, L);
@@ -953,7 +953,7 @@ struct DistLayout {
 // rounding errors add up to about eps E with eps = 2^-24 sqrt(steps / 3).  A
 // pair is flagged when eps (E_i + E_j) / (K score) could exceed tol / 2 (a
 // margin of four on the first-order score error eps (E_i + E_j) / (2 K score)).
-double dist_flag_coef(clusco_handle h, int mode, int64_t K)
+static double dist_flag_coef(clusco_handle h, int mode, int64_t K)
 {
     const double tol = h->tol[mode];
     if (mode == MODE_FP64 || !(tol > 0.0) || K < 1) return -1.0;
@@ -964,7 +964,7 @@ double dist_flag_coef(clusco_handle h, int mode, int64_t K)
     return 2.0 * eps / ((double)K * tol);
 }
 
-DistLayout dist_layout(clusco_handle h, int mode, int64_t N, int64_t L)
+static DistLayout dist_layout(clusco_handle h, int mode, int64_t N, int64_t L)
 {
     DistLayout r{};
     DistLaunch &d = r.d;
@@ -1043,6 +1043,81 @@ clusco_status clusco_drmsd_matrix(clusco_handle h, const float *coords, int64_t 
         e = launch_dist_fixup(d, st);
         if (e != hipSuccess) return hip_fail(h, e, "dRMSD fix-up launch");
     }
+    stage_mark(h, 3, st);
+    return CLUSCO_OK;
+}
+
+// ----------------------------------------------------------------- CMO
+
+namespace {
+
+struct CmoLayout {
+    CmoLaunch c;
+    size_t total;
+};
+
+static CmoLayout cmo_layout(int64_t N, int64_t L)
+{
+    CmoLayout r{};
+    CmoLaunch &c = r.c;
+    c.N = N;
+    c.Np = round_up(N > 0 ? N : 1, 256);
+    c.L = L;
+    c.K = L * (L - 1) / 2;
+    c.Kp = round_up(c.K > 0 ? c.K : 1, 32);
+    c.KB = c.Kp / 32;
+    c.nb = c.Np / 256;
+    c.T = tri_count(c.nb);
+    size_t o = 256;
+    c.off_pq = (int64_t)take(o, sizeof(uint32_t) * c.Kp);
+    c.off_n = (int64_t)take(o, sizeof(int32_t) * c.Np);
+    c.off_ops = (int64_t)take(o, (size_t)c.Np * c.Kp);
+    r.total = o;
+    return r;
+}
+
+} // namespace
+
+size_t clusco_cmo_workspace_size(clusco_handle h, int64_t N, int64_t L)
+{
+    if (!h || N < 0 || N > MAX_N || L < 1 || L > MAX_DIST_L) return 0;
+    return cmo_layout(N, L).total;
+}
+
+clusco_status clusco_cmo_matrix(clusco_handle h, const float *coords, int64_t N, int64_t L,
+                                float cutoff, float *out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (N < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0 and L >= 1");
+    if (!(cutoff >= 0.0f) || !std::isfinite(cutoff))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "cutoff must be finite and >= 0");
+    if (N > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
+    if (L > MAX_DIST_L) return fail(h, CLUSCO_ERR_UNSUPPORTED, "L above 4096");
+    if (N < 2) return CLUSCO_OK;
+    if (!coords || !out) return fail(h, CLUSCO_ERR_INVALID_ARG, "null coords or out");
+    if (!aligned(coords, 4) || !aligned(out, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "coords and out must be 4-byte aligned");
+    CmoLayout r = cmo_layout(N, L);
+    if (!ws || ws_bytes < r.total) return fail(h, CLUSCO_ERR_WORKSPACE, "workspace too small");
+    if (!aligned(ws, 256)) return fail(h, CLUSCO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    hipStream_t st = (hipStream_t)stream;
+    if (L == 1) {
+        hipError_t e = launch_zero(out, N * (N - 1) / 2, st);
+        return e == hipSuccess ? CLUSCO_OK : hip_fail(h, e, "zero launch");
+    }
+    CmoLaunch &c = r.c;
+    c.X = coords;
+    c.ws = (char *)ws;
+    c.out = out;
+    c.cutoff = cutoff;
+    stage_mark(h, 0, st);
+    stage_mark(h, 1, st);
+    hipError_t e = launch_cmo(c, st);
+    if (e != hipSuccess) return hip_fail(h, e, "CMO launch");
+    stage_mark(h, 2, st);
     stage_mark(h, 3, st);
     return CLUSCO_OK;
 }

@@ -280,6 +280,24 @@ hipError_t launch_dist_prep(int mode, const DistLaunch &a, hipStream_t s);
 hipError_t launch_dist_tile(int mode, const DistLaunch &a, hipStream_t s);
 hipError_t launch_dist_fixup(const DistLaunch &a, hipStream_t s);
 
+// All-vs-all contact map overlap (Eq. 6-7) as an integer Gram matrix.
+// Workspace regions (byte offsets): the atom pair of each distance index
+// (uint32 p | q << 16, [Kp]), the contact counts (int32 [Np]) and the int8
+// contact bits ([Np/32][KB][64 lanes][16 bytes]).
+struct CmoLaunch {
+    const float *X;       // raw coordinates [N][L][3]
+    char *ws;
+    float *out;           // packed [N(N-1)/2]
+    int64_t N, Np, L;
+    int64_t K, Kp, KB;    // atom pairs, padded to the K-block of 32, K-blocks
+    int64_t nb, T;        // 256-model tiles per side, tiles in the launch
+    int64_t off_pq, off_n, off_ops;
+    float cutoff;
+    int32_t pad;
+};
+
+hipError_t launch_cmo(const CmoLaunch &a, hipStream_t s);
+
 // Clustering of a packed score matrix (K-means with member centres).
 struct ClusterLaunch {
     const float *D;       // packed scores [N(N-1)/2]

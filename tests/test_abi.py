@@ -211,3 +211,34 @@ def test_kmedoids_sizes_and_argument_errors(L, h):
     assert f(*args(D=FAKE_ODD)) == binding.ERR_INVALID_ARG
     assert f(*args(wsb=need - 1)) == binding.ERR_WORKSPACE
     assert f(*args(ws=ctypes.c_void_p(0x10040))) == binding.ERR_INVALID_ARG
+
+
+def test_cmo_sizes_and_argument_errors(L, h):
+    K = 150 * 149 // 2
+    s = L.clusco_cmo_workspace_size(h, 1000, 150)
+    assert s % 256 == 0 and s >= 1024 * K                # one byte per (model, atom pair)
+    assert L.clusco_cmo_workspace_size(h, 10, 4097) == 0
+    assert L.clusco_cmo_workspace_size(h, 10, 0) == 0
+    f = L.clusco_cmo_matrix
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_float,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    need = L.clusco_cmo_workspace_size(h, 100, 50)
+    assert f(None, FAKE, 100, 50, 8.0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 0, 8.0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, -1.0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, float("nan"), FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, float("inf"), FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 5000, 8.0, FAKE, FAKE, need, None) == binding.ERR_UNSUPPORTED
+    assert f(h, None, 100, 50, 8.0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE_ODD, 100, 50, 8.0, FAKE, FAKE, need, None) == binding.ERR_INVALID_ARG
+    assert f(h, FAKE, 100, 50, 8.0, FAKE, FAKE, need - 1, None) == binding.ERR_WORKSPACE
+    assert f(h, None, 1, 50, 8.0, None, None, 0, None) == binding.OK
+
+
+def test_only_declared_functions_are_exported(L):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    c_names = {ln.split()[-1] for ln in out.splitlines()
+               if ln.split()[1] == "T" and not ln.split()[-1].startswith("_")}
+    assert c_names == set(declared_functions())

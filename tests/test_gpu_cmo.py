@@ -1,0 +1,89 @@
+"""GPU parity of the all-vs-all contact map overlap (Algorithms, Eq. 6-7)
+against the oracle: contact counts are exact integers on both sides and the
+score is one correctly rounded FP64 quotient, so the float32 output must equal
+the oracle's value rounded to float32, element by element."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_4000_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1302_4000_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run(cl, x, cutoff):
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    out = cl.cmo_matrix(xd, cutoff)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("cutoff", [4.0, 8.0, 12.0])
+def test_n300_l60_all_pairs_exact(cl, cutoff):
+    say(f"[cmo] N=300 L=60 all pairs, cutoff {cutoff}")
+    x = synth.make_ensemble(21, 300, 60, sigma=(0.3, 5.0)).astype(np.float32)
+    want = oracle.cmo_matrix(x, cutoff).astype(np.float32)
+    got = run(cl, x, cutoff)
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+@pytest.mark.parametrize("N,L", [(2, 2), (3, 3), (5, 7), (33, 17), (65, 33), (129, 64),
+                                 (257, 23), (300, 100)])
+def test_ragged_shapes_exact(cl, N, L):
+    say(f"[cmo] ragged N={N} L={L}")
+    x = synth.make_ensemble(3000 + N + L, N, L, sigma=(0.3, 5.0)).astype(np.float32)
+    want = oracle.cmo_matrix(x, 8.0).astype(np.float32)
+    assert np.array_equal(run(cl, x, 8.0), want)
+
+
+def test_edge_cases(cl):
+    say("[cmo] L=1, no contacts, cutoff 0, N in {0, 1}")
+    x = torch.randn(40, 1, 3, device="cuda")
+    assert torch.count_nonzero(cl.cmo_matrix(x, 8.0)).item() == 0
+    far = np.arange(20)[:, None] * np.array([10.0, 0, 0])
+    xs = np.stack([far, far * 1.1, far + 3.0]).astype(np.float32)
+    assert np.all(run(cl, xs, 5.0) == 0.0)                 # 0 / 0 -> 0
+    assert np.all(run(cl, xs, 0.0) == 0.0)
+    line = np.stack([np.arange(4)[:, None] * np.array([s, 0, 0.0]) for s in (5.0, 2.5, 3.0)])
+    got = run(cl, line.astype(np.float32), 6.0)            # worked example: 75, 100, ...
+    assert np.array_equal(got, oracle.cmo_matrix(line, 6.0).astype(np.float32))
+    assert got[0] == 75.0 and got[1] == 100.0
+    for N in (0, 1):
+        assert cl.cmo_matrix(torch.zeros(N, 10, 3, device="cuda")).numel() == 0
+
+
+def test_deterministic(cl):
+    x = synth.make_ensemble(6, 300, 50)
+    assert np.array_equal(run(cl, x, 8.0), run(cl, x, 8.0))
+
+
+def test_n20000_l150_sampled_exact(cl):
+    say("[cmo] N=20000 L=150 sampled, cutoff 8")
+    x = synth.workload("n20000_l150")
+    xd = torch.from_numpy(x).cuda()
+    out = cl.cmo_matrix(xd, 8.0)
+    rng = np.random.default_rng(5)
+    i = rng.integers(0, 20000, 20000)
+    j = rng.integers(0, 20000, 20000)
+    keep = i != j
+    I, J = np.minimum(i, j)[keep], np.maximum(i, j)[keep]
+    ii, jj = np.triu_indices(50, 1)
+    I = np.r_[I, ii, np.zeros(199, np.int64), np.arange(19800, 19999)]
+    J = np.r_[J, jj, np.arange(1, 200), np.full(199, 19999)]
+    got = out[torch.from_numpy(oracle.packed_index(I, J, 20000)).cuda()].cpu().numpy()
+    want = oracle.cmo_pairs(x, I, J, 8.0).astype(np.float32)
+    assert np.array_equal(got, want)
+    assert float(out.min()) >= 0.0 and float(out.max()) <= 100.0
