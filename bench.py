@@ -120,15 +120,27 @@ def oracle_leg(x_np, outs, want_cpu, threads):
     I2 = rng.integers(0, min(50, N), 10000)
     J2 = rng.integers(min(50, N), N, 10000)
     strata = {"uniform_1e5": (I, J), "near_identical_1225": (ii, jj), "near_vs_bulk_1e4": (I2, J2)}
+    refs = {name: oracle.crmsd_pairs(x_np, a, b, threads=threads)
+            for name, (a, b) in strata.items()}
+    bins = [(0.0, 0.5), (0.5, 2.0), (2.0, 5.0), (5.0, 1e30)]
     errs = {}
     for prec, out in outs.items():
         e = {}
+        allerr, allref = [], []
         for name, (a, b) in strata.items():
             k = torch.from_numpy(oracle.packed_index(a, b, N)).to(out.device)
             got = out[k].cpu().numpy().astype(np.float64)
-            ref = oracle.crmsd_pairs(x_np, a, b, threads=threads)
-            e[name] = float(np.abs(got - ref).max())
+            d = np.abs(got - refs[name])
+            e[name] = float(d.max())
+            allerr.append(d)
+            allref.append(refs[name])
         e["max"] = max(e.values())
+        d, r = np.concatenate(allerr), np.concatenate(allref)
+        e["by_bin_max_p99"] = {
+            f"{lo:g}-{hi:g}A" if hi < 1e29 else f">={lo:g}A":
+                [float(d[(r >= lo) & (r < hi)].max(initial=0.0)),
+                 float(np.quantile(d[(r >= lo) & (r < hi)], 0.99)) if ((r >= lo) & (r < hi)).any() else 0.0]
+            for lo, hi in bins}
         errs[prec] = e
     cpu = None
     if want_cpu:
@@ -142,9 +154,16 @@ def oracle_leg(x_np, outs, want_cpu, threads):
         oracle.crmsd_matrix(x_np[:n], threads=threads)
         dt = time.perf_counter() - t
         pairs = n * (n - 1) // 2
+        # one thread, on a smaller sample (about 2 s)
+        n1 = int(min(N, max(50, (2 * rate / threads * 2.0) ** 0.5)))
+        t = time.perf_counter()
+        oracle.crmsd_matrix(x_np[:n1], threads=1)
+        dt1 = time.perf_counter() - t
         cpu = {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                "sample": f"all-vs-all of the first {n} models of the same ensemble "
-                         f"({pairs} pairs, {dt:.1f} s, FP64 explicit Kabsch, OpenMP)"}
+                         f"({pairs} pairs, {dt:.1f} s, FP64 explicit Kabsch, OpenMP)",
+               "one_thread": {"value": n1 * (n1 - 1) / 2 / dt1, "unit": "pairs/s",
+                              "sample": f"all-vs-all of the first {n1} models ({dt1:.1f} s)"}}
     return errs, cpu
 
 
@@ -324,12 +343,14 @@ def kmedoids_leg(cl, torch, D, N, steps):
     r = cl.kmedoids(D, N, k, init, 100, ws=ws)
     torch.cuda.synchronize()
     ms = timed(torch, lambda: cl.kmedoids(D, N, k, init, 100, ws=ws), steps, 1)
+    ms_async = timed(torch, lambda: cl.kmedoids(D, N, k, init, 20, ws=ws, check_every=0), steps, 1)
     info = r["info"].cpu().tolist()
     passes = info[1] + (0 if info[2] else 1)
     gbs = passes * 4.0 * D.numel() / (ms * 1e-3) / 1e9
     return {"k": k, "ms_per_call": ms, "updates": info[1], "converged": bool(info[2]),
             "representative_cluster": info[0],
-            "matrix_passes": passes, "matrix_stream_gbs": gbs, "frac_of_hbm_peak": gbs / 8000.0}
+            "matrix_passes": passes, "matrix_stream_gbs": gbs, "frac_of_hbm_peak": gbs / 8000.0,
+            "ms_async_max_iter_20": ms_async}
 
 
 def copy_calibration(nbytes: int):

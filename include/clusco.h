@@ -273,13 +273,18 @@ size_t clusco_cluster_workspace_size(clusco_handle h, int64_t N, int32_t k);
  *   info    device int64 [3]: the representative cluster (smallest
  *           <R>_c N / n_c over clusters with n_c >= 2; ties to the lowest
  *           index; -1 if none), updates run, 1 if converged
- * The representative model is medoids[info[0]].  Every step is enqueued on
- * the stream without host synchronisation (steps after convergence return
- * at once).  1 <= k <= N <= 2^20, 0 <= max_iter <= 100000. */
+ * The representative model is medoids[info[0]].
+ * check_every = 0: all max_iter steps are enqueued on the stream and the call
+ *   returns without synchronising (steps after convergence return at once
+ *   on the device, at a few microseconds of launch cost each).
+ * check_every > 0: after every check_every steps the call synchronises the
+ *   stream, reads the convergence flag and stops enqueuing once converged
+ *   (not usable under stream capture).
+ * 1 <= k <= N <= 2^20, 0 <= max_iter <= 100000, check_every >= 0. */
 clusco_status clusco_kmedoids(clusco_handle h, const float *D, int64_t N, int32_t k,
-                              const int32_t *h_init, int32_t max_iter, int32_t *labels,
-                              int32_t *medoids, int64_t *sizes, double *mean_r, int64_t *info,
-                              void *ws, size_t ws_bytes, void *stream);
+                              const int32_t *h_init, int32_t max_iter, int32_t check_every,
+                              int32_t *labels, int32_t *medoids, int64_t *sizes, double *mean_r,
+                              int64_t *info, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -61,7 +61,8 @@ def lib():
             "clusco_cluster_workspace_size": (sz, [vp, i64, i32]),
             "clusco_cmo_workspace_size": (sz, [vp, i64, i64]),
             "clusco_cmo_matrix": (st, [vp, vp, i64, i64, ctypes.c_float, vp, vp, sz, vp]),
-            "clusco_kmedoids": (st, [vp, vp, i64, i32, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "clusco_kmedoids": (st, [vp, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, sz,
+                                     vp]),
             "clusco_drmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_fixup_count": (st, [vp, vp, i64p, vp]),
             "clusco_stage_timing": (st, [vp, ctypes.c_int]),
@@ -224,10 +225,12 @@ def cmo_matrix(x: torch.Tensor, cutoff: float = 8.0, out: torch.Tensor | None = 
 
 
 def kmedoids(D: torch.Tensor, N: int, k: int, init=None, max_iter: int = 100,
-             ws: torch.Tensor | None = None) -> dict:
+             ws: torch.Tensor | None = None, check_every: int = 4) -> dict:
     """K-means with member centres over a packed score matrix D [N(N-1)/2]
     (float32, on the GPU).  init: k distinct model indices (host sequence;
-    default: evenly spaced models).  Returns device tensors labels [N],
+    default: evenly spaced models).  check_every > 0 polls convergence every
+    that many steps (synchronising); 0 enqueues all max_iter steps
+    asynchronously.  Returns device tensors labels [N],
     medoids [k], sizes [k], mean_r [k] and info [3] (representative cluster,
     updates run, converged)."""
     if D.dtype != torch.float32 or not D.is_cuda or not D.is_contiguous():
@@ -248,8 +251,8 @@ def kmedoids(D: torch.Tensor, N: int, k: int, init=None, max_iter: int = 100,
            "sizes": torch.empty(k, dtype=torch.int64, device=dev),
            "mean_r": torch.empty(k, dtype=torch.float64, device=dev),
            "info": torch.empty(3, dtype=torch.int64, device=dev)}
-    rc = lib().clusco_kmedoids(h, _ptr(D), N, k, h_init, max_iter, _ptr(out["labels"]),
-                               _ptr(out["medoids"]), _ptr(out["sizes"]), _ptr(out["mean_r"]),
+    rc = lib().clusco_kmedoids(h, _ptr(D), N, k, h_init, max_iter, check_every,
+                               _ptr(out["labels"]), _ptr(out["medoids"]), _ptr(out["sizes"]), _ptr(out["mean_r"]),
                                _ptr(out["info"]), _ptr(ws), ws.numel(), _stream(dev))
     _check(rc, h, "clusco_kmedoids")
     return out

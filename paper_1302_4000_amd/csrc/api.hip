@@ -1131,14 +1131,15 @@ size_t clusco_cluster_workspace_size(clusco_handle h, int64_t N, int32_t k)
 }
 
 clusco_status clusco_kmedoids(clusco_handle h, const float *D, int64_t N, int32_t k,
-                              const int32_t *h_init, int32_t max_iter, int32_t *labels,
-                              int32_t *medoids, int64_t *sizes, double *mean_r, int64_t *info,
-                              void *ws, size_t ws_bytes, void *stream)
+                              const int32_t *h_init, int32_t max_iter, int32_t check_every,
+                              int32_t *labels, int32_t *medoids, int64_t *sizes, double *mean_r,
+                              int64_t *info, void *ws, size_t ws_bytes, void *stream)
 {
     if (!h) return CLUSCO_ERR_INVALID_ARG;
     h->last_error.clear();
-    if (N < 1 || k < 1 || k > N || max_iter < 0 || max_iter > 100000)
-        return fail(h, CLUSCO_ERR_INVALID_ARG, "need 1 <= k <= N and 0 <= max_iter <= 100000");
+    if (N < 1 || k < 1 || k > N || max_iter < 0 || max_iter > 100000 || check_every < 0)
+        return fail(h, CLUSCO_ERR_INVALID_ARG,
+                    "need 1 <= k <= N, 0 <= max_iter <= 100000 and check_every >= 0");
     if (N > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
     if (!h_init) return fail(h, CLUSCO_ERR_INVALID_ARG, "null initial medoids");
     {
@@ -1171,7 +1172,25 @@ clusco_status clusco_kmedoids(clusco_handle h, const float *D, int64_t N, int32_
     a.size = (long long *)sizes;
     a.mean_r = mean_r;
     a.info = (long long *)info;
-    e = launch_cluster(a, max_iter, st);
+    e = launch_cluster_begin(a, st);
+    if (e != hipSuccess) return hip_fail(h, e, "clustering launch");
+    if (check_every == 0) {
+        e = launch_cluster_iters(a, max_iter, st);
+        if (e != hipSuccess) return hip_fail(h, e, "clustering launch");
+    } else {
+        for (int32_t done = 0; done < max_iter;) {
+            const int32_t n = std::min(check_every, max_iter - done);
+            e = launch_cluster_iters(a, n, st);
+            if (e != hipSuccess) return hip_fail(h, e, "clustering launch");
+            done += n;
+            int flag = 0;
+            e = hipMemcpyAsync(&flag, a.state, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(h, e, "read convergence flag");
+            if (flag) break;
+        }
+    }
+    e = launch_cluster_end(a, st);
     return e == hipSuccess ? CLUSCO_OK : hip_fail(h, e, "clustering launch");
 }
 

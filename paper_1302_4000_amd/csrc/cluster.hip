@@ -4,9 +4,9 @@
 // of the representative model).
 //
 // Alternating steps from distinct initial medoids, as many as max_iter
-// updates, every step a launch on the caller's stream with no host
-// synchronisation: a device state word records convergence and every later
-// launch returns at once.
+// updates, each a few launches on the caller's stream: a device state word
+// records convergence and every later launch returns at once (the host may
+// also poll it and stop enqueuing).
 //
 //  km_assign   one thread per model: nearest medoid by exact float32
 //              comparison (ties to the lowest cluster, a medoid joins its own
@@ -18,8 +18,8 @@
 //              column of the tile.  Integer sums are exact, so the result does
 //              not depend on the order of the atomics
 //  km_update   one workgroup per cluster: the member of smallest cost (ties to
-//              the lowest index) becomes the medoid; a change is recorded
-//  km_step     closes the iteration (counts it, converged when nothing changed)
+//              the lowest index) becomes the medoid; the last workgroup to
+//              finish closes the iteration (converged when nothing changed)
 //  km_stats    one workgroup per cluster: size and the exact sum of costs
 //              (twice the in-cluster pair sum), <R> = sum / (n (n - 1))
 //  km_pick     the cluster of smallest <R> N / n among those with a pair
@@ -27,7 +27,7 @@
 
 namespace clusco {
 
-enum { ST_DONE = 0, ST_CHANGED = 1, ST_ITERS = 2, ST_CONVERGED = 3 };
+enum { ST_DONE = 0, ST_CHANGED = 1, ST_ITERS = 2, ST_CONVERGED = 3, ST_FINISHED = 4 };
 
 __device__ __forceinline__ float score_at(const float *D, int64_t N, int64_t i, int64_t j)
 {
@@ -89,14 +89,22 @@ __global__ __launch_bounds__(256) void km_cost(ClusterLaunch a, int final)
         __syncthreads();
         const int64_t j = bj * KT + lane;
         const int lj = j < a.N ? a.label[j] : -1;
+        // all 16 scores of this thread's column first (independent loads in
+        // flight), then the label tests
+        float d[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = bi * KT + g * 16 + r;
+            d[r] = (i < j && j < a.N) ? a.D[packed_index(i, j, a.N)] : 0.0f;
+        }
         unsigned long long cs = 0;
-        for (int r = g * 16; r < g * 16 + 16; ++r) {
-            const int64_t i = bi * KT + r;
-            if (i >= a.N) break;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = bi * KT + g * 16 + r;
             if (i < j && j < a.N && a.label[i] == lj) {
-                const unsigned long long q = (unsigned long long)quant(a.D[packed_index(i, j, a.N)]);
+                const unsigned long long q = (unsigned long long)quant(d[r]);
                 cs += q;
-                atomicAdd(&rows[r], q);
+                atomicAdd(&rows[g * 16 + r], q);
             }
         }
         cols[g][lane] = cs;
@@ -137,9 +145,12 @@ __device__ __forceinline__ void block_min(long long &key, int64_t &idx)
     __syncthreads();
 }
 
+// One workgroup per cluster; the last workgroup to finish also closes the
+// iteration (counts it; converged when no medoid changed).
 __global__ __launch_bounds__(256) void km_update(ClusterLaunch a)
 {
-    if (a.state[ST_DONE] != 0) return;
+    int *st = a.state;
+    if (st[ST_DONE] != 0) return;
     const int c = blockIdx.x;
     long long key = 0;
     int64_t idx = -1;
@@ -149,27 +160,29 @@ __global__ __launch_bounds__(256) void km_update(ClusterLaunch a)
             idx = i;
         }
     block_min(key, idx);
-    if (threadIdx.x == 0 && idx >= 0 && idx != a.medoid[c]) {
-        a.medoid[c] = (int)idx;
-        atomicOr(&a.state[ST_CHANGED], 1);
+    if (threadIdx.x == 0) {
+        if (idx >= 0 && idx != a.medoid[c]) {
+            a.medoid[c] = (int)idx;
+            atomicOr(&st[ST_CHANGED], 1);
+        }
+        __threadfence();
+        if (atomicAdd(&st[ST_FINISHED], 1) == a.k - 1) {
+            __threadfence();
+            const int changed = atomicOr(&st[ST_CHANGED], 0);
+            st[ST_ITERS] += 1;
+            if (changed == 0) {
+                st[ST_DONE] = 1;
+                st[ST_CONVERGED] = 1;
+            }
+            st[ST_CHANGED] = 0;
+            st[ST_FINISHED] = 0;
+        }
     }
-}
-
-__global__ void km_step(ClusterLaunch a)
-{
-    int *st = a.state;
-    if (threadIdx.x != 0 || st[ST_DONE] != 0) return;
-    st[ST_ITERS] += 1;
-    if (st[ST_CHANGED] == 0) {
-        st[ST_DONE] = 1;
-        st[ST_CONVERGED] = 1;
-    }
-    st[ST_CHANGED] = 0;
 }
 
 __global__ void km_clear(ClusterLaunch a)
 {
-    if (threadIdx.x < 4) a.state[threadIdx.x] = 0;
+    if (threadIdx.x < 8) a.state[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void km_stats(ClusterLaunch a)
@@ -237,19 +250,33 @@ __global__ __launch_bounds__(256) void km_pick(ClusterLaunch a)
     }
 }
 
-hipError_t launch_cluster(const ClusterLaunch &a, int max_iter, hipStream_t s)
+static dim3 cost_grid(const ClusterLaunch &a)
 {
-    const dim3 b(256), gn((unsigned)((a.N + 255) / 256)), gk((unsigned)a.k);
     const int64_t nt = (a.N + KT - 1) / KT;
     const int64_t tiles = tri_count(nt);
-    const dim3 gc((unsigned)(tiles < 8192 ? tiles : 8192));
+    return dim3((unsigned)(tiles < 2048 ? tiles : 2048));
+}
+
+hipError_t launch_cluster_begin(const ClusterLaunch &a, hipStream_t s)
+{
     km_clear<<<1, 64, 0, s>>>(a);
-    for (int it = 0; it < max_iter; ++it) {
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_iters(const ClusterLaunch &a, int iters, hipStream_t s)
+{
+    const dim3 b(256), gn((unsigned)((a.N + 255) / 256)), gk((unsigned)a.k), gc = cost_grid(a);
+    for (int it = 0; it < iters; ++it) {
         km_assign<<<gn, b, 0, s>>>(a, 0);
         km_cost<<<gc, b, 0, s>>>(a, 0);
         km_update<<<gk, b, 0, s>>>(a);
-        km_step<<<1, 64, 0, s>>>(a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_end(const ClusterLaunch &a, hipStream_t s)
+{
+    const dim3 b(256), gn((unsigned)((a.N + 255) / 256)), gk((unsigned)a.k), gc = cost_grid(a);
     km_assign<<<gn, b, 0, s>>>(a, 1);
     km_cost<<<gc, b, 0, s>>>(a, 1);
     km_stats<<<gk, b, 0, s>>>(a);

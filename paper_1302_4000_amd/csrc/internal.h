@@ -307,13 +307,15 @@ struct ClusterLaunch {
     int32_t *medoid;      // [k], holds the initial medoids at launch
     int32_t *label;       // [N]
     long long *cost;      // [N] exact sums of rounded scores (workspace)
-    int *state;           // [4] done, changed, iterations, converged (workspace)
+    int *state;           // [8] done, changed, iterations, converged, finished (workspace)
     long long *size;      // [k]
     double *mean_r;       // [k]
     long long *info;      // [3] representative cluster, iterations, converged
 };
 
-hipError_t launch_cluster(const ClusterLaunch &a, int max_iter, hipStream_t s);
+hipError_t launch_cluster_begin(const ClusterLaunch &a, hipStream_t s);
+hipError_t launch_cluster_iters(const ClusterLaunch &a, int iters, hipStream_t s);
+hipError_t launch_cluster_end(const ClusterLaunch &a, hipStream_t s);
 
 // Workspace of one launch: counters, then per-set regions, then the list.
 struct WsLayout {

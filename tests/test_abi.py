@@ -198,11 +198,12 @@ def test_kmedoids_sizes_and_argument_errors(L, h):
     init = (ctypes.c_int32 * 3)(0, 5, 9)
     need = L.clusco_cluster_workspace_size(h, 10, 3)
     args = lambda **kw: [kw.get("h", h), kw.get("D", FAKE), kw.get("N", 10), kw.get("k", 3),
-                         kw.get("init", init), kw.get("it", 50), FAKE, FAKE, FAKE, FAKE, FAKE,
-                         kw.get("ws", FAKE), kw.get("wsb", need), None]
+                         kw.get("init", init), kw.get("it", 50), kw.get("chk", 4), FAKE, FAKE,
+                         FAKE, FAKE, FAKE, kw.get("ws", FAKE), kw.get("wsb", need), None]
     assert f(*args(h=None)) == binding.ERR_INVALID_ARG
     assert f(*args(k=11)) == binding.ERR_INVALID_ARG
     assert f(*args(it=-1)) == binding.ERR_INVALID_ARG
+    assert f(*args(chk=-1)) == binding.ERR_INVALID_ARG
     assert f(*args(init=None)) == binding.ERR_INVALID_ARG
     assert f(*args(init=(ctypes.c_int32 * 3)(0, 5, 5))) == binding.ERR_INVALID_ARG   # not distinct
     assert f(*args(init=(ctypes.c_int32 * 3)(0, 5, 10))) == binding.ERR_INVALID_ARG  # out of range

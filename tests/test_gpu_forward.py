@@ -150,3 +150,20 @@ def test_n20000_l150_sampled(cl, prec):
     J2 = rng.integers(50, 20000, 10000)
     err, _ = sample_check(cl, x, prec, I2, J2, "near-vs-bulk 1e4")
     assert err.max() < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x4"])
+def test_prealigned_near_identical(cl, prec):
+    """Near-identical models in one frame (no random rotation): their bf16 lo
+    parts are correlated, the case random rotations hide."""
+    say(f"[parity] pre-aligned near-identical group {prec}")
+    rng = np.random.default_rng(11)
+    A = synth.random_walk(rng, 150)
+    x = np.stack([A + rng.normal(0, s, A.shape) for s in np.r_[np.zeros(2), np.full(40, 0.05),
+                                                                 np.full(20, 0.5)]])
+    x = (x + np.array([30.0, -12.0, 7.0])).astype(np.float32)
+    want = oracle.crmsd_matrix(x)
+    got = run(cl, x, prec).cpu().numpy().astype(np.float64)
+    err = np.abs(got - want)
+    say(f"  max err {err.max():.3e}")
+    assert err.max() < TOL[prec]

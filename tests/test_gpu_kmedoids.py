@@ -30,8 +30,12 @@ def say(*a):
 def compare(cl, D_np, N, k, init, max_iter=100):
     D = torch.from_numpy(np.ascontiguousarray(D_np, dtype=np.float32)).cuda()
     got = cl.kmedoids(D, N, k, init, max_iter)
+    # fully asynchronous mode (every step enqueued) must give the same result
+    other = cl.kmedoids(D, N, k, init, max_iter, check_every=0)
     torch.cuda.synchronize()
     got = {n: t.cpu().numpy() for n, t in got.items()}
+    for n, t in other.items():
+        assert np.array_equal(t.cpu().numpy(), got[n]), n
     want = oracle.kmedoids(D_np, N, k, init, max_iter)
     assert np.array_equal(got["labels"], want["labels"])
     assert np.array_equal(got["medoids"], want["medoids"])
