@@ -500,9 +500,15 @@ clusco_status clusco_create(clusco_handle *h, int device)
     c->tol[MODE_BF16X4] = 5e-4;
     c->tol[MODE_FP16] = 1e-4;
     c->tol[MODE_FP64] = 1e-6;
+    // effective relative error of the contraction (err * score * L / (E_i +
+    // E_j)) measured on the GPU: the largest over 2e5 pairs at L = 150 (the
+    // fix-up flag's factor-four margin covers the up to 1.8x larger maxima
+    // seen at L = 300 and the < 6e-8 of the unrefined reciprocal square
+    // roots in the tile epilogue).  A larger epsilon grows the fix-up fast:
+    // 8e-7 instead of 7e-7 for split-bf16 flags 11x more blocks at N = 20,000.
     c->eps[MODE_FP32] = 3e-7;
     c->eps[MODE_BF16] = 7e-7;
-    c->eps[MODE_BF16X4] = 2e-7;
+    c->eps[MODE_BF16X4] = 3e-7;
     c->eps[MODE_FP16] = 1.6e-7;
     c->eps[MODE_FP64] = 0.0;
     *h = c;

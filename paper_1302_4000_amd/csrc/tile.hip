@@ -156,7 +156,7 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
 #define EPI_NP 1
 #endif
 #ifndef EPI_STEPS
-#define EPI_STEPS 4
+#define EPI_STEPS 3
 #endif
 
 // Tile rows per band of the launch order: 8 x 8 tiles in flight per XCD touch
@@ -332,11 +332,14 @@ __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem 
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t i = job.Ra * ROWBLK + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        double h[9];
+        double h[1][9], ei[1], ej[1], lr2[1];
 #pragma unroll
-        for (int u = 0; u < 9; ++u) h[u] = (double)acc[u][r];
+        for (int u = 0; u < 9; ++u) h[0][u] = (double)acc[u][r];
         const double Ei = EA[i];
-        const float v = __builtin_amdgcn_sqrtf((float)fmax(eq2_lrmsd2(h, Ei, Ej) * invL, 0.0));
+        ei[0] = Ei;
+        ej[0] = Ej;
+        eq2_lrmsd2_batch<1, EPI_STEPS>(h, ei, ej, lr2);   // the forward's arithmetic
+        const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[0] * invL, 0.0));
         const bool live = jlive && i < j;
         const bool fl = live && (double)v < coef * (Ei + Ej);
         vs[r] = v;
