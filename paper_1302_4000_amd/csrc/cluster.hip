@@ -13,10 +13,10 @@
 //              cluster); clears the model's cost
 //  km_cost     one pass over the packed matrix in 64x64 pair tiles: for every
 //              pair in one cluster, q = rint(score 2^20) is added to both
-//              models' costs; row and column partial sums are combined in LDS
-//              and reach HBM through one 64-bit integer atomic per row and
-//              column of the tile.  Integer sums are exact, so the result does
-//              not depend on the order of the atomics
+//              models' costs; row sums stay in registers along a run of
+//              tiles, column sums are combined in LDS, and both reach HBM
+//              through 64-bit integer atomics.  Integer sums are exact, so the
+//              result does not depend on the order of the atomics
 //  km_update   one workgroup per cluster: the member of smallest cost (ties to
 //              the lowest index) becomes the medoid; the last workgroup to
 //              finish closes the iteration (converged when nothing changed)
@@ -71,52 +71,91 @@ __global__ __launch_bounds__(256) void km_assign(ClusterLaunch a, int final)
     a.cost[i] = 0;
 }
 
+
+// Sum of v over the 64 lanes of a wave (every lane gets the total).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 constexpr int KT = 64;   // pair tile edge of the cost pass
 
+// Each workgroup takes a contiguous run of 64x64 tiles in row-major order,
+// so a wave streams 16 packed rows along consecutive column tiles.  A thread
+// owns one column of the tile and keeps its share of the 16 row sums in
+// registers while the tile row is unchanged; the wave reduces them and one
+// 64-bit atomic per row reaches HBM when the run leaves the row.  Column sums
+// are combined over the four waves in LDS, one atomic per column and tile.
+// (Atomics across the XCDs are the expensive part: one per scattered pair
+// instead of one per column and tile is several times slower.)
 __global__ __launch_bounds__(256) void km_cost(ClusterLaunch a, int final)
 {
     const int *st = a.state;
     if (final ? st[ST_CONVERGED] != 0 : st[ST_DONE] != 0) return;
-    __shared__ unsigned long long rows[KT];
     __shared__ unsigned long long cols[4][KT];
     const int64_t nt = (a.N + KT - 1) / KT;
+    const int64_t T = tri_count(nt);
+    const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63, g = tid >> 6;
-    for (int64_t t = blockIdx.x; t < tri_count(nt); t += gridDim.x) {
-        int64_t bi, bj;
-        tri_decode(t, nt, &bi, &bj);
-        if (tid < KT) rows[tid] = 0;
-        __syncthreads();
-        const int64_t j = bj * KT + lane;
-        const int lj = j < a.N ? a.label[j] : -1;
+    const int N = (int)a.N;                     // N <= 2^20: indices fit 32 bits
+    unsigned long long racc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) racc[r] = 0;
+    int64_t bi = -1, bj = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        if (bi < 0) {
+            tri_decode(t, nt, &bi, &bj);
+        } else if (++bj == nt) {               // next tile row: flush the row sums
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const unsigned long long v = wave_sum_u64(racc[r]);
+                racc[r] = 0;
+                if (lane == 0 && v != 0)
+                    atomicAdd((unsigned long long *)&a.cost[bi * KT + g * 16 + r], v);
+            }
+            ++bi;
+            bj = bi;
+        }
+        const int j = (int)(bj * KT) + lane;
+        const int i0 = (int)(bi * KT) + g * 16;
+        const int lj = j < N ? a.label[j] : -1;
         // all 16 scores of this thread's column first (independent loads in
-        // flight), then the label tests
+        // flight), then the label tests; packed row starts advance by N - i - 2
         float d[16];
+        int64_t base = (int64_t)i0 * (2 * (int64_t)N - i0 - 1) / 2 - i0 - 1;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t i = bi * KT + g * 16 + r;
-            d[r] = (i < j && j < a.N) ? a.D[packed_index(i, j, a.N)] : 0.0f;
+            const int i = i0 + r;
+            d[r] = (i < j && j < N) ? a.D[base + j] : 0.0f;
+            base += N - i - 2;
         }
         unsigned long long cs = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t i = bi * KT + g * 16 + r;
-            if (i < j && j < a.N && a.label[i] == lj) {
-                const unsigned long long q = (unsigned long long)quant(d[r]);
-                cs += q;
-                atomicAdd(&rows[g * 16 + r], q);
-            }
+            const int i = i0 + r;
+            const unsigned long long q =
+                (i < j && j < N && a.label[i] == lj) ? (unsigned long long)quant(d[r]) : 0ull;
+            cs += q;
+            racc[r] += q;
         }
         cols[g][lane] = cs;
         __syncthreads();
         if (tid < KT) {
             const unsigned long long c = cols[0][tid] + cols[1][tid] + cols[2][tid] + cols[3][tid];
-            const int64_t jj = bj * KT + tid;
-            if (c != 0) atomicAdd((unsigned long long *)&a.cost[jj], c);
-            const int64_t ii = bi * KT + tid;
-            if (rows[tid] != 0) atomicAdd((unsigned long long *)&a.cost[ii], rows[tid]);
+            if (c != 0) atomicAdd((unsigned long long *)&a.cost[bj * KT + tid], c);
         }
         __syncthreads();
+    }
+    if (bi >= 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const unsigned long long v = wave_sum_u64(racc[r]);
+            if (lane == 0 && v != 0)
+                atomicAdd((unsigned long long *)&a.cost[bi * KT + g * 16 + r], v);
+        }
     }
 }
 
@@ -254,7 +293,7 @@ static dim3 cost_grid(const ClusterLaunch &a)
 {
     const int64_t nt = (a.N + KT - 1) / KT;
     const int64_t tiles = tri_count(nt);
-    return dim3((unsigned)(tiles < 2048 ? tiles : 2048));
+    return dim3((unsigned)(tiles < 4096 ? tiles : 4096));
 }
 
 hipError_t launch_cluster_begin(const ClusterLaunch &a, hipStream_t s)
