@@ -207,8 +207,13 @@ int bwd_mode(int mode) { return mode == MODE_FP64 ? MODE_FP32 : mode; }
 
 struct BwdLayout {
     SingleLayout s;
-    size_t off_wq, total;
+    size_t off_wq, off_pa, off_pb, off_part, total;
 };
+
+size_t grad_planes_bytes(int64_t n, int64_t L)
+{
+    return sizeof(float) * 3 * (size_t)grad_partners_padded(n) * (size_t)grad_atoms_padded(L);
+}
 
 BwdLayout bwd_layout(clusco_handle h, int mode, int64_t NA, int64_t NB, int64_t L, bool cross)
 {
@@ -217,6 +222,11 @@ BwdLayout bwd_layout(clusco_handle h, int mode, int64_t NA, int64_t NB, int64_t 
     size_t o = b.s.total;
     const int64_t pairs = cross ? NA * NB : NA * (NA - 1) / 2;
     b.off_wq = take(o, sizeof(float) * 12 * (pairs > 0 ? pairs : 1));
+    b.off_pa = take(o, grad_planes_bytes(NA, L));
+    b.off_pb = cross ? take(o, grad_planes_bytes(NB, L)) : b.off_pa;
+    size_t part = grad_partial_bytes(NA, cross ? NB : NA, L);
+    if (cross) part = std::max(part, grad_partial_bytes(NB, NA, L));
+    b.off_part = take(o, part > 0 ? part : 1);
     b.total = o;
     return b;
 }
@@ -253,14 +263,25 @@ clusco_status enqueue_bwd(clusco_handle h, int mode, const float *XA, const floa
     if (e != hipSuccess) return hip_fail(h, e, "backward pairs launch");
     const double *cenA = (const double *)(ws + b.s.A.cen);
     const double *cenB = (const double *)(ws + b.s.B.cen);
-    const int64_t NA = b.s.p.NA, NB = b.s.p.NB, L = b.s.p.L;
-    GradLaunch ga{XA, cross ? XB : XA, cenA, cross ? cenB : cenA, tl.wq, gradA, NA,
-                  cross ? NB : NA, L, cross ? GK_CROSS_A : GK_SYM, 0};
-    e = launch_grad(ga, s);
+    const int64_t NA = b.s.p.NA, NB = b.s.p.NB, L = b.s.p.L, Lp = grad_atoms_padded(L);
+    float *PA = (float *)(ws + b.off_pa), *PB = (float *)(ws + b.off_pb);
+    e = launch_grad_planes(XA, cenA, PA, NA, L, s);
+    if (e == hipSuccess && cross) e = launch_grad_planes(XB, cenB, PB, NB, L, s);
+    if (e != hipSuccess) return hip_fail(h, e, "gradient planes launch");
+    // the two sides run one after the other on the stream and share the partials
+    auto side = [&](const float *XR, const double *cenR, const float *P, float *grad, int64_t NR,
+                    int64_t NC, int kind) {
+        const GradSplit sp = grad_split(NR, NC, L);
+        const size_t nw = (size_t)sp.nsplit * (size_t)NR;
+        double *part = (double *)(ws + b.off_part);
+        GradLaunch gl{XR, cenR, P, tl.wq, grad, part, part + 3 * L * nw, NR, NC, L, Lp, kind,
+                      sp.nsplit, sp.bps, 0};
+        return launch_grad(gl, s);
+    };
+    e = side(XA, cenA, cross ? PB : PA, gradA, NA, cross ? NB : NA, cross ? GK_CROSS_A : GK_SYM);
     if (e != hipSuccess) return hip_fail(h, e, "gradient launch");
     if (cross && gradB) {
-        GradLaunch gb{XB, XA, cenB, cenA, tl.wq, gradB, NB, NA, L, GK_CROSS_B, 0};
-        e = launch_grad(gb, s);
+        e = side(XB, cenB, PA, gradB, NB, NA, GK_CROSS_B);
         if (e != hipSuccess) return hip_fail(h, e, "gradient launch");
     }
     return CLUSCO_OK;

@@ -227,13 +227,21 @@ enum TileOp { OP_FWD = 0, OP_BWD = 1, OP_THR = 2 };
 // with Q~ = Q of the record, or its transpose when m is the second model of
 // the pair.
 struct GradLaunch {
-    const float *XR, *XC;     // raw coordinates of rows / partners
-    const double *cenR, *cenC;
+    const float *XR;          // raw coordinates of the row models
+    const double *cenR;       // their centroids
+    const float *P;           // centred partner planes [j][d][Lp]
     const float *wq;          // per-pair records
     float *grad;              // [NR][L][3]
-    int64_t NR, NC, L;
+    double *part;             // [nsplit][NR][L][3] partial G (nsplit > 1)
+    double *wpart;            // [nsplit][NR] partial weight sums (nsplit > 1)
+    int64_t NR, NC, L, Lp;
     int32_t kind;             // GK_SYM, GK_CROSS_A, GK_CROSS_B
+    int32_t nsplit, bps;      // partner ranges and partner blocks per range
     int32_t pad;
+};
+
+struct GradSplit {
+    int32_t nsplit, bps;
 };
 
 enum GradKind { GK_SYM = 0, GK_CROSS_A = 1, GK_CROSS_B = 2 };
@@ -328,6 +336,12 @@ struct WsLayout {
 hipError_t launch_prep(const PrepLaunch &a, hipStream_t s);
 hipError_t launch_tile(int mode, const TileLaunch &a, hipStream_t s, int op = OP_FWD);
 hipError_t launch_grad(const GradLaunch &a, hipStream_t s);
+hipError_t launch_grad_planes(const float *X, const double *cen, float *P, int64_t N, int64_t L,
+                              hipStream_t s);
+int64_t grad_partners_padded(int64_t n);
+GradSplit grad_split(int64_t NR, int64_t NC, int64_t L);
+size_t grad_partial_bytes(int64_t NR, int64_t NC, int64_t L);
+int64_t grad_atoms_padded(int64_t L);
 hipError_t launch_zero(float *p, int64_t n, hipStream_t s);
 hipError_t launch_fixup(const FixupLaunch &a, hipStream_t s);
 
