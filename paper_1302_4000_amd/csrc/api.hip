@@ -274,7 +274,7 @@ clusco_status enqueue_bwd(clusco_handle h, int mode, const float *XA, const floa
         const GradSplit sp = grad_split(NR, NC, L);
         const size_t nw = (size_t)sp.nsplit * (size_t)NR;
         double *part = (double *)(ws + b.off_part);
-        GradLaunch gl{XR, cenR, P, tl.wq, grad, part, part + 3 * L * nw, NR, NC, L, Lp, kind,
+        GradLaunch gl{XR, cenR, (const float4 *)P, tl.wq, grad, part, part + 3 * L * nw, NR, NC, L, Lp, kind,
                       sp.nsplit, sp.bps, 0};
         return launch_grad(gl, s);
     };

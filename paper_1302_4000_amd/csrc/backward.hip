@@ -17,21 +17,27 @@
 // when the partners surround the model (a reference against many noisy
 // copies of itself).
 //
-//  grad_planes  centred partner coordinates as float planes P[j][d][l] (atoms
-//               padded with zeros to 16, partners to a multiple of 32), so
-//               that the flattened contraction index k = 3j + d addresses row
-//               k of a plain row-major matrix
+//  grad_planes  centred partner coordinates in the B fragment layout (atoms
+//               padded with zeros to 16, partners to a multiple of 32): per
+//               partner block and 16-atom tile, 16-byte chunks holding a
+//               lane's values for four consecutive steps, lane-major, so a
+//               wave fetches four steps of a fragment with one coalesced
+//               load.  Contraction index k = 3j + d (partner j, coordinate d)
 //  grad_kernel  one workgroup = 16 models x 256 atoms x a range of partner
 //               blocks (the whole range unless few row models), 8 waves, each owning
 //               two 16-atom column tiles and all three coordinate row tiles
 //               (6 accumulators).  Per block of 32 partners the 512 pair
-//               records (one per thread) are staged to LDS as the A operand
+//               records (one per thread) are staged to LDS as the A operand,
+//               the three coordinate rows of a (k, m) entry side by side so
+//               that a lane reads its three fragments with one 16-byte load
 //               (double-buffered, one barrier per block); B fragments come
-//               straight from the planes into registers one block ahead.
-//               The weights w are summed per model from the same staging.
+//               straight from the planes into registers half a block ahead.
+//               Each thread also sums the weights w of the pairs it stages.
 //  grad_finish  with several partner ranges: FP64 partials summed in range
 //               order (deterministic), then the gradient.
 #include "internal.h"
+
+#include <type_traits>
 
 namespace clusco {
 
@@ -44,24 +50,35 @@ constexpr int GKS = GKB / 4;          // MFMA steps per block
 constexpr int GW = 8;                 // waves per workgroup
 constexpr int GCT = 2;                // 16-atom column tiles per wave
 constexpr int GLC = 16 * GW * GCT;    // atoms per workgroup (256)
-constexpr int ARS = 3 * GBM + 1;      // LDS row stride of the staged weights
+constexpr int GQ = GKS / 4;           // 16-byte B chunks per lane per block and atom tile
 static_assert(GBM * GBJ == 64 * GW, "one pair record per thread per block");
+static_assert(GKS % 8 == 0, "two halves of whole 16-byte chunks");
 
+// One thread per 16-byte chunk: chunk (blk, t, q, lane) holds, for lane
+// (g, i) = (lane / 16, lane % 16), the B fragment values of steps s = 4q + e,
+// e = 0..3, of partner block blk and atom tile t: contraction row k = 4s + g
+// (partner 32 blk + k / 3, coordinate k % 3), atom 16 t + i.
 __global__ __launch_bounds__(256) void grad_planes_kernel(const float *X, const double *cen,
-                                                          float *P, int64_t N, int64_t Np,
-                                                          int64_t L, int64_t Lp)
+                                                          float4 *P, int64_t N, int64_t nblk,
+                                                          int64_t L, int64_t NT)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Np * Lp) return;
-    const int64_t j = t / Lp, l = t % Lp;
-    float v[3] = {0.0f, 0.0f, 0.0f};
-    if (j < N && l < L) {
-        const float *x = X + (j * L + l) * 3;
+    if (t >= nblk * NT * GQ * 64) return;
+    const int lane = (int)(t & 63);
+    const int q = (int)((t >> 6) % GQ);
+    const int64_t tile = (t / (64 * GQ)) % NT;
+    const int64_t blk = t / (64 * GQ * NT);
+    const int g = lane >> 4;
+    const int64_t l = 16 * tile + (lane & 15);
+    float v[4];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) v[d] = (float)((double)x[d] - cen[3 * j + d]);
+    for (int e = 0; e < 4; ++e) {
+        const int k = 4 * (4 * q + e) + g;
+        const int64_t j = blk * GBJ + k / 3;
+        const int d = k % 3;
+        v[e] = (j < N && l < L) ? (float)((double)X[(j * L + l) * 3 + d] - cen[3 * j + d]) : 0.0f;
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) P[(j * 3 + d) * Lp + l] = v[d];
+    P[t] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
 // The record of pair (m, j) seen from row model m: its index and whether the
@@ -87,8 +104,7 @@ __device__ __forceinline__ bool grad_pair(const GradLaunch &a, int64_t m, int64_
 
 __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
 {
-    __shared__ float As[2][GKB * ARS];    // A operand: [k = 3 j + d][row = 16 c + m]
-    __shared__ float Ws[2][GBJ * GBM];    // weights w: [j][m]
+    __shared__ float4 As[2][GKB * GBM];   // A operand: [k = 3 j + d][m] -> (c = 0, 1, 2, pad)
     __shared__ double wfin[GBM];
     __shared__ double wred[64 * GW];
 
@@ -102,59 +118,66 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
     const int b0 = split * a.bps;
     const int b1 = min(nblk, b0 + a.bps);
 
-    // column tiles of this wave (wave-uniform validity)
-    bool colv[GCT];
-    int64_t col[GCT];
+    // column tiles of this wave: the first nct are inside the padded atoms
+    // (wave-uniform); the others load column 0 and skip their products, so
+    // that every load is unconditional and the waits stay exact
+    int64_t col[GCT], colc[GCT];
+    int nct = 0;
 #pragma unroll
     for (int ct = 0; ct < GCT; ++ct) {
         col[ct] = l0 + 16 * (w + GW * ct);
-        colv[ct] = col[ct] < Lp;
+        const bool in = col[ct] < Lp;
+        colc[ct] = in ? col[ct] : 0;
+        nct += in ? 1 : 0;
     }
     const int g = lane >> 4, i16 = lane & 15;
 
-    // staging: one pair per thread; the mapping keeps a wave's records
-    // contiguous in memory (consecutive j for a row, or consecutive m when
-    // the rows are the pairs' second models)
-    auto stage_map = [&](int blk, int *ml, int *jl) {
-        const int64_t j0 = (int64_t)blk * GBJ;
-        const bool trblk = a.kind == GK_CROSS_B || (a.kind == GK_SYM && j0 + GBJ <= m0);
-        if (trblk) {
-            *ml = tid % GBM;
-            *jl = tid / GBM;
-        } else {
-            *jl = tid % GBJ;
-            *ml = tid / GBJ;
-        }
+    // staging: one pair per thread, thread t = (pair model m = t % 16,
+    // partner j = t / 16); a wave covers 4 consecutive partners of all 16
+    // models, so its loads are 16 runs of 4 consecutive records (or 4 runs
+    // of 16 when the rows are the pairs' second models) and its LDS stores
+    // are contiguous.  Missing pairs load record 0 and store zeros.
+    const int sml = tid % GBM, sjl = tid / GBM;
+    struct Staged {
+        float4 r[3];
+        bool ok, tr;
     };
-    auto stage_load = [&](int blk, int ml, int jl, float4 *r, bool *tr) -> bool {
-        int64_t k;
-        if (!grad_pair(a, m0 + ml, (int64_t)blk * GBJ + jl, &k, tr)) return false;
-        const float4 *p = (const float4 *)(a.wq + 12 * k);
-        r[0] = p[0];
-        r[1] = p[1];
-        r[2] = p[2];
-        return true;
+    auto stage_load = [&](int blk, Staged &st) {
+        int64_t k = 0;
+        st.tr = false;
+        st.ok = grad_pair(a, m0 + sml, (int64_t)blk * GBJ + sjl, &k, &st.tr);
+        const float4 *p = (const float4 *)(a.wq + 12 * (st.ok ? k : 0));
+        st.r[0] = p[0];
+        st.r[1] = p[1];
+        st.r[2] = p[2];
     };
-    auto stage_store = [&](int buf, int ml, int jl, const float4 *r4, bool ok, bool tr) {
+    // row c of the A operand at contraction index (j, d) is Q~[c][d]
+    auto stage_store = [&](int buf, const Staged &st, double &wsum) {
         float r[10];
-        r[0] = r4[0].x; r[1] = r4[0].y; r[2] = r4[0].z; r[3] = r4[0].w;
-        r[4] = r4[1].x; r[5] = r4[1].y; r[6] = r4[1].z; r[7] = r4[1].w;
-        r[8] = r4[2].x; r[9] = r4[2].y;
-        float *A = As[buf] + (3 * jl) * ARS + ml;
+        r[0] = st.r[0].x; r[1] = st.r[0].y; r[2] = st.r[0].z; r[3] = st.r[0].w;
+        r[4] = st.r[1].x; r[5] = st.r[1].y; r[6] = st.r[1].z; r[7] = st.r[1].w;
+        r[8] = st.r[2].x; r[9] = st.r[2].y;
+        float4 *A = As[buf] + (3 * sjl) * GBM + sml;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+            float q[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-                A[d * ARS + 16 * c] = ok ? (tr ? r[3 * d + c] : r[3 * c + d]) : 0.0f;
-        Ws[buf][jl * GBM + ml] = ok ? r[9] : 0.0f;
+            for (int c = 0; c < 3; ++c) q[c] = st.ok ? (st.tr ? r[3 * d + c] : r[3 * c + d]) : 0.0f;
+            A[d * GBM] = make_float4(q[0], q[1], q[2], 0.0f);
+        }
+        wsum += st.ok ? (double)r[9] : 0.0;
     };
-    auto load_b = [&](int blk, float (*bq)[GCT]) {
-        const float *P = a.P + ((int64_t)blk * GKB + g) * Lp + i16;
+    // B fragments of half a block (GKH steps) into registers: GQ / 2
+    // coalesced 16-byte loads per column tile
+    constexpr int GKH = GKS / 2;
+    const int64_t NT = Lp / 16;
+    auto load_half = [&](int blk, int h, float4 (*bq)[GCT]) {
 #pragma unroll
-        for (int s = 0; s < GKS; ++s)
+        for (int ct = 0; ct < GCT; ++ct) {
+            const float4 *P = a.P + (((int64_t)blk * NT + colc[ct] / 16) * GQ + h * (GQ / 2)) * 64 + lane;
 #pragma unroll
-            for (int ct = 0; ct < GCT; ++ct)
-                bq[s][ct] = colv[ct] ? P[(int64_t)(4 * s) * Lp + col[ct]] : 0.0f;
+            for (int q = 0; q < GQ / 2; ++q) bq[q][ct] = P[q * 64];
+        }
     };
 
     f64x4 acc[3][GCT];
@@ -164,51 +187,55 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
         for (int ct = 0; ct < GCT; ++ct) acc[c][ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
     double wpart = 0.0;
 
-    float bcur[GKS][GCT], bnext[GKS][GCT];
-    {
-        int ml, jl;
-        float4 r[3];
-        bool tr = false;
-        stage_map(b0, &ml, &jl);
-        const bool ok = stage_load(b0, ml, jl, r, &tr);
-        stage_store(0, ml, jl, r, ok, tr);
-        load_b(b0, bcur);
-    }
-    __syncthreads();
-
-    for (int blk = b0; blk < b1; ++blk) {
-        const int buf = (blk - b0) & 1;
-        const bool more = blk + 1 < b1;
-        int ml = 0, jl = 0;
-        float4 r[3];
-        bool ok = false, tr = false;
-        if (more) {
-            stage_map(blk + 1, &ml, &jl);
-            ok = stage_load(blk + 1, ml, jl, r, &tr);
-            load_b(blk + 1, bnext);
-        }
-        const float *A = As[buf] + g * ARS + i16;
+    // the unrolled contraction over half a block for the first NT column tiles
+    auto kloop = [&](const float4 *A, const float4 (*bq)[GCT], auto NT) {
 #pragma unroll
-        for (int s = 0; s < GKS; ++s) {
-            double af[3];
+        for (int s = 0; s < GKH; ++s) {
+            const float4 q = A[(4 * s) * GBM];
+            const double af[3] = {(double)q.x, (double)q.y, (double)q.z};
 #pragma unroll
-            for (int c = 0; c < 3; ++c) af[c] = (double)A[(4 * s) * ARS + 16 * c];
-#pragma unroll
-            for (int ct = 0; ct < GCT; ++ct) {
-                if (!colv[ct]) continue;
-                const double bf = (double)bcur[s][ct];
+            for (int ct = 0; ct < decltype(NT)::value; ++ct) {
+                const float4 b4 = bq[s / 4][ct];
+                const double bf = (double)(s % 4 == 0 ? b4.x : s % 4 == 1 ? b4.y : s % 4 == 2 ? b4.z : b4.w);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     acc[c][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[c], bf, acc[c][ct], 0, 0, 0);
             }
         }
-        wpart += (double)Ws[buf][tid];
-        if (more) stage_store(buf ^ 1, ml, jl, r, ok, tr);
+    };
+    auto khalf = [&](const float4 *A, const float4 (*bq)[GCT]) {
+        if (nct == GCT) kloop(A, bq, std::integral_constant<int, GCT>{});
+        else if (nct == 1) kloop(A, bq, std::integral_constant<int, 1>{});
+    };
+
+    // two register halves in fixed roles: b0h holds the first half of the
+    // current block (fetched during the previous block), b1h its second half
+    float4 b0h[GQ / 2][GCT], b1h[GQ / 2][GCT];
+    {
+        Staged st;
+        stage_load(b0, st);
+        stage_store(0, st, wpart);
+        load_half(b0, 0, b0h);
+    }
+    __syncthreads();
+
+    for (int blk = b0; blk < b1; ++blk) {
+        const int buf = (blk - b0) & 1;
+        // prefetch the next block (the last block refetches itself: every
+        // load stays unconditional; its staging buffer is not read again)
+        const int nxt = blk + 1 < b1 ? blk + 1 : blk;
+        // second-half fragments first: waits on them then never wait on the
+        // (older) record loads as well
+        load_half(blk, 1, b1h);
+        Staged st;
+        stage_load(nxt, st);
+        const float4 *A = As[buf] + g * GBM + i16;
+        khalf(A, b0h);
+        load_half(nxt, 0, b0h);
+        khalf(A + 4 * GKH * GBM, b1h);
+        double wdummy = 0.0;
+        stage_store(buf ^ 1, st, blk + 1 < b1 ? wpart : wdummy);
         __syncthreads();
-#pragma unroll
-        for (int s = 0; s < GKS; ++s)
-#pragma unroll
-            for (int ct = 0; ct < GCT; ++ct) bcur[s][ct] = bnext[s][ct];
     }
 
     // sum of the weights per model, in a fixed order
@@ -229,7 +256,7 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
         a.wpart[(int64_t)split * a.NR + m0 + tid] = wfin[tid];
 #pragma unroll
     for (int ct = 0; ct < GCT; ++ct) {
-        if (!colv[ct]) continue;
+        if (ct >= nct) continue;
         const int64_t l = col[ct] + i16;
         if (l >= a.L) continue;
 #pragma unroll
@@ -261,6 +288,7 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(GradLaunch a)
     if (t >= a.NR * a.L) return;
     const int64_t m = t / a.L;
     double ws = 0.0, gs[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int sp = 0; sp < a.nsplit; ++sp) {
         ws += a.wpart[(int64_t)sp * a.NR + m];
         const double *pm = a.part + ((int64_t)sp * a.NR * a.L + t) * 3;
@@ -286,9 +314,10 @@ int64_t grad_atoms_padded(int64_t L) { return round_up(L, 16); }
 hipError_t launch_grad_planes(const float *X, const double *cen, float *P, int64_t N,
                               int64_t L, hipStream_t s)
 {
-    const int64_t Np = grad_partners_padded(N), Lp = grad_atoms_padded(L);
-    grad_planes_kernel<<<dim3((unsigned)((Np * Lp + 255) / 256)), dim3(256), 0, s>>>(X, cen, P, N, Np,
-                                                                                     L, Lp);
+    const int64_t nblk = grad_partners_padded(N) / GBJ, NT = grad_atoms_padded(L) / 16;
+    const int64_t chunks = nblk * NT * GQ * 64;
+    grad_planes_kernel<<<dim3((unsigned)((chunks + 255) / 256)), dim3(256), 0, s>>>(
+        X, cen, (float4 *)P, N, nblk, L, NT);
     return hipGetLastError();
 }
 

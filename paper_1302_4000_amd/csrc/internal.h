@@ -229,7 +229,7 @@ enum TileOp { OP_FWD = 0, OP_BWD = 1, OP_THR = 2 };
 struct GradLaunch {
     const float *XR;          // raw coordinates of the row models
     const double *cenR;       // their centroids
-    const float *P;           // centred partner planes [j][d][Lp]
+    const float4 *P;          // centred partner coordinates, B fragment layout
     const float *wq;          // per-pair records
     float *grad;              // [NR][L][3]
     double *part;             // [nsplit][NR][L][3] partial G (nsplit > 1)
