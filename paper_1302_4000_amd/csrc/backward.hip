@@ -11,11 +11,13 @@
 // The second term is one matrix product per workgroup of 16 models:
 //     G[(c, m), l] = sum over (j, d) of  Q~_mj[c][d] * b_j[l][d],
 // rows (coordinate c, model m), contraction over (partner j, coordinate d),
-// columns atoms l.  It runs on v_mfma_f64_16x16x4_f64: FP64 products of the
-// FP32 records and centred FP32 coordinates, FP64 accumulation in a fixed
-// order (deterministic).  FP64 matters here: the two terms nearly cancel
-// when the partners surround the model (a reference against many noisy
-// copies of itself).
+// columns atoms l.  It runs on v_mfma_f32_16x16x4_f32 over blocks of 32
+// partners (96 contraction terms, FP32 accumulation from zero), and each
+// block's result is added to FP64 accumulators in block order
+// (deterministic).  The FP64 fold matters: the two terms nearly cancel when
+// the partners surround the model (a reference against many noisy copies of
+// itself), so the running sum must not carry FP32 rounding of its full
+// magnitude; a block's FP32 sum carries only that of 1/128 of it (N = 4096).
 //
 //  grad_planes  centred partner coordinates in the B fragment layout (atoms
 //               padded with zeros to 16, partners to a multiple of 32): per
@@ -41,7 +43,7 @@
 
 namespace clusco {
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int GBM = 16;               // models per workgroup (one MFMA row tile per coordinate)
 constexpr int GBJ = 32;               // partners per staged block
@@ -180,11 +182,17 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
         }
     };
 
-    f64x4 acc[3][GCT];
+    // FP32 block accumulators and the FP64 running sums they are folded into
+    f32x4 acc[3][GCT];
+    double sum[3][GCT][4];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int ct = 0; ct < GCT; ++ct) acc[c][ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        for (int ct = 0; ct < GCT; ++ct) {
+            acc[c][ct] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sum[c][ct][v] = 0.0;
+        }
     double wpart = 0.0;
 
     // the unrolled contraction over half a block for the first NT column tiles
@@ -192,14 +200,14 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
 #pragma unroll
         for (int s = 0; s < GKH; ++s) {
             const float4 q = A[(4 * s) * GBM];
-            const double af[3] = {(double)q.x, (double)q.y, (double)q.z};
+            const float af[3] = {q.x, q.y, q.z};
 #pragma unroll
             for (int ct = 0; ct < decltype(NT)::value; ++ct) {
                 const float4 b4 = bq[s / 4][ct];
-                const double bf = (double)(s % 4 == 0 ? b4.x : s % 4 == 1 ? b4.y : s % 4 == 2 ? b4.z : b4.w);
+                const float bf = s % 4 == 0 ? b4.x : s % 4 == 1 ? b4.y : s % 4 == 2 ? b4.z : b4.w;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    acc[c][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[c], bf, acc[c][ct], 0, 0, 0);
+                    acc[c][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[c], bf, acc[c][ct], 0, 0, 0);
             }
         }
     };
@@ -233,6 +241,14 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
         khalf(A, b0h);
         load_half(nxt, 0, b0h);
         khalf(A + 4 * GKH * GBM, b1h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int ct = 0; ct < GCT; ++ct) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sum[c][ct][v] += (double)acc[c][ct][v];
+                acc[c][ct] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+            }
         double wdummy = 0.0;
         stage_store(buf ^ 1, st, blk + 1 < b1 ? wpart : wdummy);
         __syncthreads();
@@ -248,8 +264,8 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
     }
     __syncthreads();
 
-    // epilogue: accumulator element v of a lane is G row (c, m = lane / 16 + 4 v),
-    // column l = col + lane % 16 (the f64 16x16x4 output layout).  With one
+    // epilogue: accumulator element v of a lane is G row (c, m = 4 (lane / 16) + v),
+    // column l = col + lane % 16 (the f32 16x16x4 output layout).  With one
     // split the gradient is finished here; otherwise this split's weight sums
     // and G go to FP64 partials that grad_finish adds in split order.
     if (a.nsplit > 1 && tid < GBM && m0 + tid < a.NR)
@@ -261,13 +277,13 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
         if (l >= a.L) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int mm = g + 4 * v;
+            const int mm = 4 * g + v;
             const int64_t m = m0 + mm;
             if (m >= a.NR) continue;
             if (a.nsplit > 1) {
                 double *pm = a.part + (((int64_t)split * a.NR + m) * a.L + l) * 3;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pm[c] = acc[c][ct][v];
+                for (int c = 0; c < 3; ++c) pm[c] = sum[c][ct][v];
                 continue;
             }
             const float *xm = a.XR + (m * a.L + l) * 3;
@@ -275,7 +291,7 @@ __global__ __launch_bounds__(512, 1) void grad_kernel(GradLaunch a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double am = (double)xm[c] - a.cenR[3 * m + c];
-                gm[c] = (float)(wfin[mm] * am - acc[c][ct][v]);
+                gm[c] = (float)(wfin[mm] * am - sum[c][ct][v]);
             }
         }
     }

@@ -502,7 +502,7 @@ __device__ __forceinline__ void stage_store(u32x4 *slot, int tid,
     for (int m = 0; m < StageGeom<MODE>::PER; ++m) slot[tid + 256 * m] = pre[m];
 }
 
-template <int MODE, int KIND>
+template <int MODE, int KIND, int OP>
 __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
 {
     using G = StageGeom<MODE>;
@@ -606,30 +606,34 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     job.pidx = 0;
     job.active = !(p.sym && bi == bj && wy > wx) && job.Ra * ROWBLK < p.NA &&
                  job.Rb * ROWBLK < p.NB;
-    if (job.active) epilogue(a, p, job, lane, acc);
+    if (job.active) {
+        if constexpr (OP == OP_BWD) bwd_epilogue(a, p, job, lane, acc);
+        else if constexpr (OP == OP_THR) thr_epilogue(a, p, job, lane, acc);
+        else epilogue(a, p, job, lane, acc);
+    }
 }
 
 template <int MODE>
 static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, int op)
 {
     dim3 g((unsigned)grid), b(512);
+    const dim3 sg((unsigned)round_up(a.T > 0 ? a.T : 1, 8)), sb(256);
     if (op == OP_THR) {
         if (a.kind != TK_SYM) return hipErrorInvalidValue;
-        tile_kernel<MODE, TK_SYM, OP_THR><<<g, b, 0, s>>>(a);
+        staged_kernel<MODE, TK_SYM, OP_THR><<<sg, sb, 0, s>>>(a);
         return hipGetLastError();
     }
     if (op == OP_BWD) {
-        if (a.kind == TK_SYM) tile_kernel<MODE, TK_SYM, OP_BWD><<<g, b, 0, s>>>(a);
-        else if (a.kind == TK_RECT) tile_kernel<MODE, TK_RECT, OP_BWD><<<g, b, 0, s>>>(a);
+        if (a.kind == TK_SYM) staged_kernel<MODE, TK_SYM, OP_BWD><<<sg, sb, 0, s>>>(a);
+        else if (a.kind == TK_RECT) staged_kernel<MODE, TK_RECT, OP_BWD><<<sg, sb, 0, s>>>(a);
         else return hipErrorInvalidValue;
         return hipGetLastError();
     }
     switch (a.kind) {
     case TK_SYM:
     case TK_RECT: {
-        const dim3 sg((unsigned)round_up(a.T > 0 ? a.T : 1, 8)), sb(256);
-        if (a.kind == TK_SYM) staged_kernel<MODE, TK_SYM><<<sg, sb, 0, s>>>(a);
-        else staged_kernel<MODE, TK_RECT><<<sg, sb, 0, s>>>(a);
+        if (a.kind == TK_SYM) staged_kernel<MODE, TK_SYM, OP_FWD><<<sg, sb, 0, s>>>(a);
+        else staged_kernel<MODE, TK_RECT, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
     }
     default: tile_kernel<MODE, TK_BATCH, OP_FWD><<<g, b, 0, s>>>(a); break;
