@@ -209,14 +209,29 @@ def backward_leg(cl, torch, steps):
     g = torch.full((P,), 1.0 / P, device="cuda")
     gt = torch.full((N, 1), 1.0 / N, device="cuda")
     res = {"workload": "n4096_l256", "N": N, "L": L, "pairs": P}
+    dev = x.device.index
     for prec in ("fp32", "bf16"):
         out = cl.crmsd_matrix(x, prec)
         fwd = timed(torch, lambda: cl.crmsd_matrix(x, prec, out=out), steps, 1)
-        bwd = timed(torch, lambda: cl.crmsd_backward(x, out, g, prec), steps, 1)
+        cl.crmsd_backward(x, out, g, prec)
+        torch.cuda.synchronize()
+        cl.binding.stage_timing(dev, steps)
+        bwd = timed(torch, lambda: cl.crmsd_backward(x, out, g, prec), steps, 0)
+        stage_ms, ncalls = cl.binding.stage_times(dev)
+        cl.binding.stage_timing(dev, 0)
+        assert ncalls == steps
+        pairs_ms, grad_ms = stage_ms[1] / steps, stage_ms[2] / steps
+        # gradient contraction: 9 multiply-adds per (model, partner, atom),
+        # FP32 MFMA with an FP64 fold per partner block
+        grad_tf = 18.0 * N * (N - 1) * L / (grad_ms * 1e-3) / 1e12
         tv = cl.crmsd_cross(x, ref, prec)
         tfwd = timed(torch, lambda: cl.crmsd_cross(x, ref, prec, out=tv), steps, 1)
         tbwd = timed(torch, lambda: cl.crmsd_cross_backward(x, ref, tv, gt, prec), steps, 1)
         res[prec] = {"forward_ms": fwd, "backward_ms": bwd,
+                     "backward_stages_ms": {"prep": stage_ms[0] / steps, "pairs_pass": pairs_ms,
+                                            "gradient_pass": grad_ms},
+                     "gradient_tflops": grad_tf,
+                     "gradient_frac_of_fp32_mfma_peak": grad_tf / PEAK_TFLOPS["fp32"],
                      "fwd_bwd_pairs_per_s": P / ((fwd + bwd) * 1e-3),
                      "target_vs_many_forward_ms": tfwd, "target_vs_many_backward_ms": tbwd}
     return res
@@ -377,6 +392,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and backward measurements")
+    ap.add_argument("--leg", choices=["backward"], default=None,
+                    help="only run one supporting measurement and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter scaling)")
     args = ap.parse_args()
@@ -395,6 +412,11 @@ def main():
 
     import paper_1302_4000_amd as cl
     from paper_1302_4000_amd import synth
+
+    if args.leg == "backward":
+        log("[bench] backward only: N=4096 L=256")
+        print(json.dumps({"leg": "backward", **backward_leg(cl, torch, args.steps)}), flush=True)
+        return
 
     log(f"[bench] generating {args.workload}")
     x_np = synth.workload(args.workload)

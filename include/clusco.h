@@ -126,12 +126,15 @@ clusco_status clusco_fixup_count(clusco_handle h, const void *ws, int64_t *count
 /* Stage timing for measurement.  With max_calls > 0, the next max_calls
  * forward calls (all-vs-all, batched, cross) on this handle record HIP events
  * on their stream around their three stages: prep, contraction + epilogue,
- * and fix-up.  Creates 4 * max_calls events once; 0 disables and frees them. */
+ * and fix-up; backward calls (all-vs-all, cross) around prep, the pairs pass
+ * (contraction + adjoint records) and the gradient pass.  Creates
+ * 4 * max_calls events once; 0 disables and frees them. */
 clusco_status clusco_stage_timing(clusco_handle h, int max_calls);
 
 /* Sum of the recorded stage durations (ms) over the calls recorded since
- * timing was enabled or last read: ms[0] prep, ms[1] contraction + epilogue,
- * ms[2] fix-up; *calls = how many calls were recorded.  Synchronises on the
+ * timing was enabled or last read: ms[0] prep, ms[1] contraction + epilogue
+ * (backward: pairs pass), ms[2] fix-up (backward: gradient pass); *calls =
+ * how many calls were recorded.  Synchronises on the
  * last recorded event and restarts the recording. */
 clusco_status clusco_stage_times(clusco_handle h, double ms[3], int *calls);
 

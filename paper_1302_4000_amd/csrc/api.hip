@@ -235,6 +235,7 @@ clusco_status enqueue_bwd(clusco_handle h, int mode, const float *XA, const floa
                           char *ws, const BwdLayout &b, bool cross, const float *rmsd,
                           const float *gout, float *gradA, float *gradB, hipStream_t s)
 {
+    const bool timing = h->used < h->slots;
     const int m = bwd_mode(mode);
     PrepLaunch pl{};
     pl.XA = XA;
@@ -246,8 +247,10 @@ clusco_status enqueue_bwd(clusco_handle h, int mode, const float *XA, const floa
     pl.set[1] = b.s.B;
     pl.nset = cross ? 2 : 1;
     pl.total = b.s.A.Np + (cross ? b.s.B.Np : 0);
+    if (timing) stage_mark(h, 0, s);
     hipError_t e = launch_prep(pl, s);
     if (e != hipSuccess) return hip_fail(h, e, "prep launch");
+    if (timing) stage_mark(h, 1, s);
     TileLaunch tl{};
     tl.ws = ws;
     tl.prob = b.s.p;
@@ -261,6 +264,7 @@ clusco_status enqueue_bwd(clusco_handle h, int mode, const float *XA, const floa
     tl.wq = (float *)(ws + b.off_wq);
     e = launch_tile(m, tl, s, OP_BWD);
     if (e != hipSuccess) return hip_fail(h, e, "backward pairs launch");
+    if (timing) stage_mark(h, 2, s);
     const double *cenA = (const double *)(ws + b.s.A.cen);
     const double *cenB = (const double *)(ws + b.s.B.cen);
     const int64_t NA = b.s.p.NA, NB = b.s.p.NB, L = b.s.p.L, Lp = grad_atoms_padded(L);
@@ -284,6 +288,7 @@ clusco_status enqueue_bwd(clusco_handle h, int mode, const float *XA, const floa
         e = side(XB, cenB, PA, gradB, NB, NA, GK_CROSS_B);
         if (e != hipSuccess) return hip_fail(h, e, "gradient launch");
     }
+    if (timing) stage_mark(h, 3, s);
     return CLUSCO_OK;
 }
 
