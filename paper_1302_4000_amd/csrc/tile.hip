@@ -159,9 +159,12 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
 #define EPI_STEPS 3
 #endif
 
-// Tile rows per band of the launch order: 8 x 8 tiles in flight per XCD touch
-// about 2 MB of operands, well inside its 4 MB L2.
-constexpr int64_t BAND = 8;
+// Tile rows per band of the launch order.  A band's column sweep re-reads
+// the column operands once per band, so wider bands fetch less, until the
+// band's row operands and the columns in flight outgrow the XCD's 4 MB L2:
+// at N = 20,000, L = 150 (split-BF16) 8 rows fetched 0.77 GB per launch,
+// 16 rows 0.44 GB (and ran 4% faster), 32 rows 3.8 GB.
+constexpr int64_t BAND = 16;
 
 // A wave's share of one 64x64 tile: its 32x32 block and the problem.
 struct WaveJob {
@@ -204,22 +207,43 @@ __device__ __forceinline__ WaveJob decode_job(const TileLaunch &a, int64_t t, in
     return job;
 }
 
+// The radii a wave's epilogue needs, loaded once (not once per pair, which
+// would put a dependent memory round trip in front of every pair): E of the
+// lane's column j = Rb*32 + lane%32, and E of row Ra*32 + lane%32, from which
+// each pair takes its row's radius with a cross-lane shuffle.
+struct EpiRadii {
+    double ej, erow;
+};
+
+__device__ __forceinline__ EpiRadii epi_radii(const TileLaunch &a, const Problem &p,
+                                              const WaveJob &job, int lane)
+{
+    const double *EA = (const double *)(a.ws + p.EA);
+    const double *EB = (const double *)(a.ws + p.EB);
+    return EpiRadii{EB[job.Rb * ROWBLK + (lane & 31)], EA[job.Ra * ROWBLK + (lane & 31)]};
+}
+
+// E of row Ra*32 + r (r < 32) from the lane that loaded it.
+__device__ __forceinline__ double row_radius(const EpiRadii &er, int r)
+{
+    return __shfl(er.erow, r, 64);
+}
+
 // FP64 Eq. 2 epilogue and store of one wave's 32x32 block.  The lane holds
 // column j = lane%32 and rows 8(r/4) + 4(lane/32) + r%4 of accumulator slot r.
 // Every slot is evaluated (padding rows and columns have H = 0 and E = 0,
 // which is finite); only the store and the flag are predicated, so the FP64
 // work runs without divergent branches.
 __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
-                                         const WaveJob &job, int lane, const f32x16 acc[9])
+                                         const WaveJob &job, int lane, const f32x16 acc[9],
+                                         const EpiRadii &er)
 {
     const int64_t NA = p.NA, NB = p.NB;
-    const double *EA = (const double *)(a.ws + p.EA);
-    const double *EB = (const double *)(a.ws + p.EB);
     float *out = a.out + p.out;
     const double invL = 1.0 / (double)p.L;
     const double coef = p.flag_coef;
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
-    const double Ej = EB[j];
+    const double Ej = er.ej;
     const bool jlive = j < (p.sym ? NA : NB);
     bool flagged = false;
 #pragma unroll
@@ -234,7 +258,7 @@ __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
             for (int b = 0; b < EPI_NP; ++b) {
 #pragma unroll
                 for (int u = 0; u < 9; ++u) h[b][u] = (double)acc[u][4 * g + q0 + b];
-                ei[b] = EA[i0 + q0 + b];
+                ei[b] = row_radius(er, 8 * g + 4 * (lane >> 5) + q0 + b);
                 ej[b] = Ej;
             }
             eq2_lrmsd2_batch<EPI_NP, EPI_STEPS>(h, ei, ej, lr2);
@@ -261,14 +285,13 @@ __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
 // is 0 to within 1e-5 of the pair's mean radius, where cRMSD is not
 // differentiable) and the adjoint Q of the pair's H; writes [w Q, w, 0, 0].
 __device__ __forceinline__ void bwd_epilogue(const TileLaunch &a, const Problem &p,
-                                             const WaveJob &job, int lane, const f32x16 acc[9])
+                                             const WaveJob &job, int lane, const f32x16 acc[9],
+                                             const EpiRadii &er)
 {
     const int64_t NA = p.NA, NB = p.NB;
-    const double *EA = (const double *)(a.ws + p.EA);
-    const double *EB = (const double *)(a.ws + p.EB);
     const double L = (double)p.L;
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
-    const double Ej = EB[j];
+    const double Ej = er.ej;
     const bool jlive = j < (p.sym ? NA : NB);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -282,7 +305,7 @@ __device__ __forceinline__ void bwd_epilogue(const TileLaunch &a, const Problem 
             if (live) {
                 const int64_t k = base + j;
                 const double sc = (double)a.rmsd[k], gk = (double)a.gout[k];
-                const double floor_r = 1e-5 * sqrt((EA[i] + Ej) / (2.0 * L));
+                const double floor_r = 1e-5 * sqrt((row_radius(er, 8 * g + 4 * (lane >> 5) + q) + Ej) / (2.0 * L));
                 const double w = (gk != 0.0 && sc > floor_r) ? gk / (L * sc) : 0.0;
                 float rec[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
                 if (w != 0.0) {
@@ -316,16 +339,15 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long b)
 // its prefix position).  Pairs the fix-up will recompute are not emitted
 // here; their bits go into the block's ownership mask with the list entry.
 __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem &p,
-                                             const WaveJob &job, int lane, const f32x16 acc[9])
+                                             const WaveJob &job, int lane, const f32x16 acc[9],
+                                             const EpiRadii &er)
 {
     const int64_t NA = p.NA;
-    const double *EA = (const double *)(a.ws + p.EA);
-    const double *EB = (const double *)(a.ws + p.EB);
     const double invL = 1.0 / (double)p.L;
     const double coef = p.flag_coef;
     const float cutoff = (float)a.emit.cutoff;
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
-    const double Ej = EB[j];
+    const double Ej = er.ej;
     const bool jlive = j < NA;
     float vs[16];
     uint32_t emit = 0, flag = 0;
@@ -335,7 +357,7 @@ __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem 
         double h[1][9], ei[1], ej[1], lr2[1];
 #pragma unroll
         for (int u = 0; u < 9; ++u) h[0][u] = (double)acc[u][r];
-        const double Ei = EA[i];
+        const double Ei = row_radius(er, 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
         ei[0] = Ei;
         ej[0] = Ej;
         eq2_lrmsd2_batch<1, EPI_STEPS>(h, ei, ej, lr2);   // the forward's arithmetic
@@ -444,9 +466,11 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
                 contract<MODE>(a.ws + p.opsA, a.ws + p.opsB, job.Ra, job.Rb, p.KB, lane, acc);
             }
         } else if (job.active) {
-            if constexpr (OP == OP_FWD) epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
-            else if constexpr (OP == OP_BWD) bwd_epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
-            else thr_epilogue(a, problem_of<KIND>(a, job.pidx), job, lane, acc);
+            const Problem &pe = problem_of<KIND>(a, job.pidx);
+            const EpiRadii er = epi_radii(a, pe, job, lane);
+            if constexpr (OP == OP_FWD) epilogue(a, pe, job, lane, acc, er);
+            else if constexpr (OP == OP_BWD) bwd_epilogue(a, pe, job, lane, acc, er);
+            else thr_epilogue(a, pe, job, lane, acc, er);
             job.active = 0;
         }
     }
@@ -458,12 +482,11 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
 // workgroup, two workgroups per CU.  The operand chunks of the tile's two
 // row blocks of A and two of B for one K-block (24 KiB in the split modes)
 // are staged in a 3-slot LDS ring: each chunk reaches the CU once instead of
-// once per wave that reads it, and loads run two K-blocks ahead.  Each wave
-// then runs the FP64 epilogue of its 32x32 block.  The two workgroups of a
-// CU are independent, so one's MFMA contraction overlaps the other's FP64
-// epilogue.
-
-constexpr int RING = 3;
+// once per wave that reads it.  They travel straight from global memory to
+// LDS (no registers) and are issued two K-blocks ahead, so a K-block's loads
+// have a whole step of contraction to land.  Each wave then runs the FP64
+// epilogue of its 32x32 block.  The two workgroups of a CU are independent,
+// so one's MFMA contraction overlaps the other's FP64 epilogue.
 
 template <int MODE>
 struct StageGeom {
@@ -473,40 +496,53 @@ struct StageGeom {
     static constexpr int PER = SLOT / 256;              // u32x4 loads per thread
 };
 
-// Thread tid's PER u32x4 of K-block kb of the tile whose first row blocks of
-// A and B are rA and rB (row block R, K-block kb: chunk base (R*KB + kb)*REGION).
+// Thread tid's PER chunks (u32x4) of K-block kb of the tile whose first row
+// blocks of A and B are rA and rB (row block R, K-block kb: chunk base
+// (R*KB + kb)*REGION), sent straight from global memory to the LDS slot
+// (global_load_lds_dwordx4, no registers): load m of wave w moves 64
+// consecutive chunks, lane l's 16 bytes landing at slot + 256 m + 64 w + l.
+// The wave's 64 chunks always lie in one region (REGION is a multiple of 64).
+// kb < 0 issues the same number of loads from the first chunks of A (always
+// present, cached), so that every step has the same count in flight; the
+// slot they fill is not read again.
 template <int MODE>
-__device__ __forceinline__ void stage_load(const Problem &p, const char *ws, int64_t rA,
-                                           int64_t rB, int64_t kb, int tid,
-                                           u32x4 (&pre)[StageGeom<MODE>::PER])
+__device__ __forceinline__ void stage_dma(const Problem &p, const char *ws, int64_t rA,
+                                          int64_t rB, int64_t kb, int tid, int w, u32x4 *slot)
 {
     using G = StageGeom<MODE>;
     const int64_t KB = p.KB;
-    const u32x4 *rowA = (const u32x4 *)(ws + p.opsA) + (rA * KB + kb) * G::REGION;
-    const u32x4 *rowB = (const u32x4 *)(ws + p.opsB) + (rB * KB + kb) * G::REGION;
+    const bool live = kb >= 0;
+    const u32x4 *ops = (const u32x4 *)(ws + p.opsA);
+    const u32x4 *rowA = ops + (rA * KB + (live ? kb : 0)) * G::REGION;
+    const u32x4 *rowB = (const u32x4 *)(ws + p.opsB) + (rB * KB + (live ? kb : 0)) * G::REGION;
     const int64_t next = KB * G::REGION;            // the next row block, same K-block
 #pragma unroll
     for (int m = 0; m < G::PER; ++m) {
         const int q = tid + 256 * m;
         const int region = q / G::REGION, off = q % G::REGION;
-        const u32x4 *base = region < 2 ? rowA : rowB;
-        pre[m] = base[(region & 1) * next + off];
+        const u32x4 *src = live ? (region < 2 ? rowA : rowB) + (region & 1) * next + off : ops + off;
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
+                                         (void __attribute__((address_space(3))) *)(slot + 256 * m + 64 * w),
+                                         16, 0, 0);
     }
 }
 
-template <int MODE>
-__device__ __forceinline__ void stage_store(u32x4 *slot, int tid,
-                                            const u32x4 (&pre)[StageGeom<MODE>::PER])
+// s_waitcnt vmcnt(N) alone (expcnt and lgkmcnt left free), N <= 63.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
 {
-#pragma unroll
-    for (int m = 0; m < StageGeom<MODE>::PER; ++m) slot[tid + 256 * m] = pre[m];
+    static_assert(N >= 0 && N < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
 template <int MODE, int KIND, int OP>
 __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
 {
     using G = StageGeom<MODE>;
-    __shared__ u32x4 ring[RING][G::SLOT];
+    // three ring slots as separate arrays (fixed per unrolled step below), so
+    // that the compiler can tell the loads in flight into one slot from the
+    // reads of another and adds no wait for them
+    __shared__ u32x4 slot0[G::SLOT], slot1[G::SLOT], slot2[G::SLOT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wy = w >> 1, wx = w & 1;
@@ -521,29 +557,35 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     else band_decode_rect(t, p.nbA, p.nbB, BAND, &bi, &bj);
     const int64_t KB = p.KB;
 
-    {
-        u32x4 pre[G::PER];
-        stage_load<MODE>(p, a.ws, 2 * bi, 2 * bj, 0, tid, pre);
-        stage_store<MODE>(ring[0], tid, pre);
-        if (KB > 1) {
-            stage_load<MODE>(p, a.ws, 2 * bi, 2 * bj, 1, tid, pre);
-            stage_store<MODE>(ring[1], tid, pre);
-        }
-    }
-    __syncthreads();
+    WaveJob job;
+    job.Ra = 2 * bi + wy;
+    job.Rb = 2 * bj + wx;
+    job.pidx = 0;
+    job.active = !(p.sym && bi == bj && wy > wx) && job.Ra * ROWBLK < p.NA &&
+                 job.Rb * ROWBLK < p.NB;
+    // the epilogue's radii, loaded with the first K-blocks
+    const EpiRadii er = epi_radii(a, p, job, lane);
+    stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 0, tid, w, slot0);
+    if (KB > 1) stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 1, tid, w, slot1);
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
 
     f32x16 acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-    for (int64_t kb = 0; kb < KB; ++kb) {
-        const bool more = kb + 2 < KB;
-        u32x4 pre[G::PER];
-        if (more) stage_load<MODE>(p, a.ws, 2 * bi, 2 * bj, kb + 2, tid, pre);
+    // One K-block from slot cur; the loads of K-block kb + 2 go into nxt
+    // (the slot read one step earlier, released by that step's barrier) and
+    // stay in flight across the next step: at the end of this step only the
+    // loads of K-block kb + 1 (issued one step earlier) must have landed.
+    // The barrier needs no memory fence: each wave's own waits order its
+    // loads, and the LDS reads are complete once their MFMAs have issued.
+    auto step = [&](int64_t kb, const u32x4 *cur, u32x4 *nxt) {
+        stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, kb + 2 < KB ? kb + 2 : -1, tid, w, nxt);
         pin_order();
-        const u32x4 *sA = &ring[kb % RING][wy * G::REGION + lane];
-        const u32x4 *sB = &ring[kb % RING][(2 + wx) * G::REGION + lane];
+        const u32x4 *sA = cur + wy * G::REGION + lane;
+        const u32x4 *sB = cur + (2 + wx) * G::REGION + lane;
         if constexpr (MODE == MODE_FP32) {
             f32x4 A[3], B[3];
 #pragma unroll
@@ -595,21 +637,28 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
                 for (int d = 0; d < 3; ++d)
                     acc[3 * c + d] = mfma_split<MODE>(Al[c], Bh[d], acc[3 * c + d]);
         }
-        pin_order();
-        if (more) stage_store<MODE>(ring[(kb + 2) % RING], tid, pre);
-        __syncthreads();
+        // the wait and barrier stay behind the MFMAs (the scheduler would
+        // otherwise hoist them, shortening the distance the loads get)
+        __builtin_amdgcn_sched_barrier(0);
+        wait_vmcnt<G::PER>();
+        __builtin_amdgcn_s_barrier();
+    };
+    // whole rounds of three steps, then the remainder: every round ends with
+    // the step into slot 2, so the compiler sees slot 0 complete at the top
+    int64_t kb = 0;
+    for (; kb + 3 <= KB; kb += 3) {
+        step(kb, slot0, slot2);
+        step(kb + 1, slot1, slot0);
+        step(kb + 2, slot2, slot1);
     }
+    if (kb < KB) step(kb, slot0, slot2);
+    if (kb + 1 < KB) step(kb + 1, slot1, slot0);
+    wait_vmcnt<0>();    // no load into LDS outlives the workgroup
 
-    WaveJob job;
-    job.Ra = 2 * bi + wy;
-    job.Rb = 2 * bj + wx;
-    job.pidx = 0;
-    job.active = !(p.sym && bi == bj && wy > wx) && job.Ra * ROWBLK < p.NA &&
-                 job.Rb * ROWBLK < p.NB;
     if (job.active) {
-        if constexpr (OP == OP_BWD) bwd_epilogue(a, p, job, lane, acc);
-        else if constexpr (OP == OP_THR) thr_epilogue(a, p, job, lane, acc);
-        else epilogue(a, p, job, lane, acc);
+        if constexpr (OP == OP_BWD) bwd_epilogue(a, p, job, lane, acc, er);
+        else if constexpr (OP == OP_THR) thr_epilogue(a, p, job, lane, acc, er);
+        else epilogue(a, p, job, lane, acc, er);
     }
 }
 
