@@ -565,6 +565,10 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
                  job.Rb * ROWBLK < p.NB;
     // the epilogue's radii, loaded with the first K-blocks
     const EpiRadii er = epi_radii(a, p, job, lane);
+    // the contraction runs at a raised wave priority: a SIMD's other wave is
+    // usually in its FP64 epilogue, and the MFMA issue should not wait behind
+    // that stream of VALU instructions
+    __builtin_amdgcn_s_setprio(3);
     stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 0, tid, w, slot0);
     if (KB > 1) stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 1, tid, w, slot1);
     wait_vmcnt<0>();
@@ -610,8 +614,18 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
             for (int c = 0; c < 3; ++c) {
                 Ah[c] = sA[(2 * c) * 64];
                 Bh[c] = sB[(2 * c) * 64];
-                Bl[c] = sB[(2 * c + 1) * 64];
             }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Bl[c] = sB[(2 * c + 1) * 64];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Al[c] = sA[(2 * c + 1) * 64];
+            // the hi operands are read first and the first nine products
+            // wait only for them; the lo operands land meanwhile
+            __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -622,8 +636,6 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
                     acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Al[c] = sA[(2 * c + 1) * 64];
             if constexpr (MODE == MODE_BF16X4) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -654,6 +666,7 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     if (kb < KB) step(kb, slot0, slot2);
     if (kb + 1 < KB) step(kb + 1, slot1, slot0);
     wait_vmcnt<0>();    // no load into LDS outlives the workgroup
+    __builtin_amdgcn_s_setprio(0);
 
     if (job.active) {
         if constexpr (OP == OP_BWD) bwd_epilogue(a, p, job, lane, acc, er);
