@@ -6,7 +6,7 @@
 // below flag_coef (E_i + E_j); this kernel re-evaluates that test on the
 // stored scores of each listed block, compacts the flagged pairs in LDS and
 // recomputes each one from the raw float32 coordinates entirely in FP64
-// (see pair_fp64), then the same Eq. 2 epilogue.  With `all` set (FP64 precision) every pair
+// (see pair_fp64_span), then the same Eq. 2 epilogue.  With `all` set (FP64 precision) every pair
 // of every block is computed this way.  In threshold mode the candidates are
 // the pairs the tile kernel marked in the block's ownership mask, and the
 // recomputed pairs below the cutoff are appended to the output arrays.
@@ -18,32 +18,34 @@ namespace clusco {
 // cRMSD of one pair entirely in FP64 from the raw float32 coordinates:
 // H = sum_l x_l y_l^T - L c_x c_y^T (the centred correlation; in FP64 the
 // cancellation against translations of ~100 A costs about one digit) and
-// the exact FP64 radii computed once per model by the prep pass.
-__device__ __forceinline__ float pair_fp64(const float *xi, const float *xj, const double *ci,
-                                           const double *cj, double ea, double eb, int64_t L)
+// the exact FP64 radii computed once per model by the prep pass.  The atoms
+// are split over FIX_SPAN lanes (lane sl takes atoms sl, sl + FIX_SPAN, ...:
+// consecutive lanes read consecutive atoms), the partial correlations summed
+// by a fixed xor butterfly (reproducible); every lane of the group then
+// holds the whole H and runs the epilogue.
+constexpr int FIX_SPAN = 16;
+
+__device__ __forceinline__ float pair_fp64_span(const float *xi, const float *xj, const double *ci,
+                                                const double *cj, double ea, double eb, int64_t L,
+                                                int sl)
 {
     double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t l = 0;
-    for (; l + 1 < L; l += 2) {
-        double a[6], b[6];
+    for (int64_t l = sl; l < L; l += FIX_SPAN) {
+        double a[3], b[3];
 #pragma unroll
-        for (int u = 0; u < 6; ++u) {
+        for (int u = 0; u < 3; ++u) {
             a[u] = (double)xi[3 * l + u];
             b[u] = (double)xj[3 * l + u];
         }
 #pragma unroll
         for (int p = 0; p < 3; ++p)
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
-                h[3 * p + q] = fma(a[p], b[q], fma(a[3 + p], b[3 + q], h[3 * p + q]));
+            for (int q = 0; q < 3; ++q) h[3 * p + q] = fma(a[p], b[q], h[3 * p + q]);
     }
-    if (l < L) {
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+    for (int off = FIX_SPAN / 2; off > 0; off >>= 1)
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
-                h[3 * p + q] = fma((double)xi[3 * l + p], (double)xj[3 * l + q], h[3 * p + q]);
-    }
+        for (int u = 0; u < 9; ++u) h[u] += __shfl_xor(h[u], off, FIX_SPAN);
     const double dl = (double)L;
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -55,6 +57,7 @@ __device__ __forceinline__ float pair_fp64(const float *xi, const float *xj, con
 
 // One workgroup of FIX_THREADS per listed block at a time.
 constexpr int FIX_THREADS = 256;
+constexpr int FIX_PAIRS = FIX_THREADS / FIX_SPAN;   // pairs in flight per workgroup
 
 __global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
 {
@@ -113,20 +116,21 @@ __global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
         const double *cenB = (const double *)(a.ws + p.cenB);
         const double *E64A = (const double *)(a.ws + p.E64A);
         const double *E64B = (const double *)(a.ws + p.E64B);
-        for (int s0 = 0; s0 < m; s0 += FIX_THREADS) {   // uniform trip count (ballots below)
-            const int s = s0 + tid;
+        const int ps = tid / FIX_SPAN, sl = tid % FIX_SPAN;
+        for (int s0 = 0; s0 < m; s0 += FIX_PAIRS) {   // uniform trip count (ballots below)
+            const int s = s0 + ps;
             int64_t i = 0, j = 0;
             float v = 0.0f;
-            if (s < m) {
+            if (s < m) {          // uniform over each group of FIX_SPAN lanes
                 const int q = todo[s];
                 i = Ra * ROWBLK + (q >> 5);
                 j = Rb * ROWBLK + (q & 31);
-                v = pair_fp64(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j, E64A[i],
-                              E64B[j], L);
-                if (!a.thr) out[p.sym ? packed_index(i, j, NA) : i * NB + j] = v;
+                v = pair_fp64_span(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j,
+                                   E64A[i], E64B[j], L, sl);
+                if (!a.thr && sl == 0) out[p.sym ? packed_index(i, j, NA) : i * NB + j] = v;
             }
             if (a.thr) {
-                const bool em = s < m && v < (float)a.emit.cutoff;
+                const bool em = s < m && sl == 0 && v < (float)a.emit.cutoff;
                 const unsigned long long b = __ballot(em);
                 if (b) {
                     unsigned long long base = 0;
