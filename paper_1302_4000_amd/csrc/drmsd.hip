@@ -140,22 +140,38 @@ __device__ __forceinline__ f32x16 mfma16(u32x4 x, u32x4 y, f32x16 c)
 
 __device__ __forceinline__ void pin() { asm volatile("" ::: "memory"); }
 
+// s_waitcnt vmcnt(N) lgkmcnt(0) (expcnt left free), N <= 63.
+template <int N>
+__device__ __forceinline__ void dist_wait_vm_lgkm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
 constexpr int GT = 256;            // models per workgroup tile edge
 constexpr int GB = GT / ROWBLK;    // 32-model blocks per tile edge
 
-// One 256x256 pair tile per 8-wave workgroup.  Per K-block the workgroup
-// stages the operand chunks of its 8 row blocks and 8 column blocks in LDS
-// (double-buffered; the next K-block's chunks are loaded into registers while
-// the current one is multiplied), and each wave multiplies 2 row blocks by 4
-// column blocks (64 x 128 pairs, eight 32x32 accumulators).  Every chunk
-// reaches the CU once per K-block instead of once per wave that uses it.
+// One 256x256 pair tile per 8-wave workgroup; each wave multiplies 2 row
+// blocks by 4 column blocks (64 x 128 pairs, eight 32x32 accumulators).  Per
+// K-block the workgroup's operand chunks (its 8 row blocks and 8 column
+// blocks) go straight from global memory into a 3-slot LDS ring
+// (global_load_lds_dwordx4: load m of wave w moves chunk w + 8 m, lane l's 16
+// bytes landing at chunk base + 16 l), issued three K-blocks ahead; every
+// chunk reaches the CU once per K-block instead of once per wave that uses
+// it.  A wave reads the next K-block's fragments from LDS into a second
+// register set while the current K-block's MFMAs run.  Step s: loads of
+// K-block s + 3 into the slot read at step s - 1, reads of slot s + 1, the
+// MFMAs of K-block s, then a wait for the loads of K-block s + 2 only and a
+// bare barrier.  The slots are separate LDS arrays used in a loop unrolled
+// by three (slot fixed per step) with the same number of loads in every
+// step, so the compiler adds no waits of its own.
 template <int MODE>
 __global__ __launch_bounds__(512, 1) void dist_tile_kernel(DistLaunch a)
 {
     constexpr int P = is_split(MODE) ? 2 : 1;      // chunk parts (hi, lo)
     constexpr int NCH = 2 * GB * P;                // chunks per K-block, A then B
-    constexpr int PER = NCH / 8;                   // chunk loads per thread
-    __shared__ u32x4 lds[2][NCH][64];
+    constexpr int PER = NCH / 8;                   // chunk loads per wave
+    __shared__ u32x4 slot0[NCH * 64], slot1[NCH * 64], slot2[NCH * 64];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, in scalars
@@ -178,13 +194,30 @@ __global__ __launch_bounds__(512, 1) void dist_tile_kernel(DistLaunch a)
         const int64_t R = (side ? bj : bi) * GB + r / P;
         src[m] = (R * KB * P + r % P) * 64;
     }
-    const u32x4 *opl = ops + lane;
-    u32x4 pre[PER];
+    // K-block kb into a slot; kb >= KB loads the first chunks of the operand
+    // array (present, cached) into a slot nobody reads again
+    auto dma = [&](int64_t kb, u32x4 *slot) {
 #pragma unroll
-    for (int m = 0; m < PER; ++m) pre[m] = opl[src[m]];
+        for (int m = 0; m < PER; ++m) {
+            const u32x4 *g = (kb < KB ? ops + src[m] + kb * P * 64 : ops) + lane;
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                             (void __attribute__((address_space(3))) *)(slot + (w + 8 * m) * 64),
+                                             16, 0, 0);
+        }
+    };
+    struct Frag {
+        u32x4 a[2 * P], b[4 * P];
+    };
+    auto read = [&](const u32x4 *slot, Frag &f) {
 #pragma unroll
-    for (int m = 0; m < PER; ++m) lds[0][w + 8 * m][lane] = pre[m];
-    __syncthreads();
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int h = 0; h < P; ++h) f.a[s * P + h] = slot[((2 * wy + s) * P + h) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int h = 0; h < P; ++h) f.b[u * P + h] = slot[(GB * P + (4 * wx + u) * P + h) * 64 + lane];
+    };
 
     f32x16 acc[2][4];
 #pragma unroll
@@ -193,79 +226,92 @@ __global__ __launch_bounds__(512, 1) void dist_tile_kernel(DistLaunch a)
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[s][u][r] = 0.0f;
-
-    for (int64_t kb = 0; kb < KB; ++kb) {
-        const int buf = (int)(kb & 1);
-        const bool more = kb + 1 < KB;
-        if (more) {
+    auto mma = [&](const Frag &f) {
+        if constexpr (MODE == MODE_FP32) {
 #pragma unroll
-            for (int m = 0; m < PER; ++m) pre[m] = opl[src[m] + (kb + 1) * P * 64];
-        }
-        pin();
-        {
-            if constexpr (MODE == MODE_FP32) {
-                f32x4 A[2], B[4];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) A[s] = __builtin_bit_cast(f32x4, lds[buf][2 * wy + s][lane]);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) B[u] = __builtin_bit_cast(f32x4, lds[buf][GB + 4 * wx + u][lane]);
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int s = 0; s < 2; ++s)
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            acc[s][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s][e], B[u][e],
-                                                                            acc[s][u], 0, 0, 0);
-            } else {
-                u32x4 Ah[2], Al[2], Bh[4], Bl[4];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    Ah[s] = lds[buf][(2 * wy + s) * 2][lane];
-                    Al[s] = lds[buf][(2 * wy + s) * 2 + 1][lane];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    Bh[u] = lds[buf][2 * GB + (4 * wx + u) * 2][lane];
-                    Bl[u] = lds[buf][2 * GB + (4 * wx + u) * 2 + 1][lane];
-                }
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Ah[s], Bh[u], acc[s][u]);
+                    for (int u = 0; u < 4; ++u)
+                        acc[s][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            __builtin_bit_cast(f32x4, f.a[s])[e], __builtin_bit_cast(f32x4, f.b[u])[e],
+                            acc[s][u], 0, 0, 0);
+        } else {
+            // hi*hi', hi*lo', lo*hi' (lo*lo' in x4 mode)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(f.a[2 * s], f.b[2 * u], acc[s][u]);
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(f.a[2 * s], f.b[2 * u + 1], acc[s][u]);
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(f.a[2 * s + 1], f.b[2 * u], acc[s][u]);
+            if constexpr (MODE == MODE_BF16X4) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Ah[s], Bl[u], acc[s][u]);
-#pragma unroll
-                for (int s = 0; s < 2; ++s)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Al[s], Bh[u], acc[s][u]);
-                if constexpr (MODE == MODE_BF16X4) {
-#pragma unroll
-                    for (int s = 0; s < 2; ++s)
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[s][u] = mfma16<MODE>(Al[s], Bl[u], acc[s][u]);
-                }
+                    for (int u = 0; u < 4; ++u)
+                        acc[s][u] = mfma16<MODE>(f.a[2 * s + 1], f.b[2 * u + 1], acc[s][u]);
             }
         }
-        if (more) {
-#pragma unroll
-            for (int m = 0; m < PER; ++m) lds[buf ^ 1][w + 8 * m][lane] = pre[m];
-        }
-        __syncthreads();
+    };
+    // one step: cur holds K-block s (read at the previous step) and gets
+    // K-block s + 1 at the end; sd is the slot of K-block s (free: read last
+    // step), sr the slot of K-block s + 1
+    Frag cur;
+    auto step = [&](int64_t s, u32x4 *sd, const u32x4 *sr) {
+        dma(s + 3, sd);
+        Frag nxt;
+        read(sr, nxt);
+        mma(cur);
+        // both barriers' work: the loads of K-block s + 2 have landed (those
+        // of s + 3 stay in flight) and this wave's reads of slot s + 1 are
+        // done before another wave's loads may overwrite it
+        __builtin_amdgcn_sched_barrier(0);
+        dist_wait_vm_lgkm<PER>();
+        __builtin_amdgcn_s_barrier();
+        cur = nxt;
+    };
+
+    dma(0, slot0);
+    dma(1, slot1);
+    dma(2, slot2);
+    dist_wait_vm_lgkm<PER>();          // K-blocks 0 and 1 have landed
+    __builtin_amdgcn_s_barrier();
+    read(slot0, cur);
+    int64_t s = 0;
+    for (; s + 3 <= KB; s += 3) {
+        step(s, slot0, slot1);
+        step(s + 1, slot1, slot2);
+        step(s + 2, slot2, slot0);
     }
+    if (s < KB) step(s, slot0, slot1);
+    if (s + 1 < KB) step(s + 1, slot1, slot2);
+    dist_wait_vm_lgkm<0>();            // no load into LDS outlives the workgroup
+
+    // the epilogue's radii: E of the wave's 64 rows (two per lane, shuffled
+    // to each pair) and of its lane's four columns, in one batch of loads
+    const double *E = (const double *)(a.ws + a.off_E);
+    double erow[2], ecol[4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) erow[s] = E[(bi * GB + 2 * wy + s) * ROWBLK + (lane & 31)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ecol[u] = E[(bj * GB + 4 * wx + u) * ROWBLK + (lane & 31)];
     if (idle) return;
 
     // epilogue: lane holds column j = lane%32, rows 8(r/4) + 4(lane/32) + r%4
-    const double *E = (const double *)(a.ws + a.off_E);
     const int64_t N = a.N;
     const double invK = 1.0 / (double)a.K;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int64_t C = bj * GB + 4 * wx + u;
         const int64_t j = C * ROWBLK + (lane & 31);
-        const double Ej = E[j];
+        const double Ej = ecol[u];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int64_t R = bi * GB + 2 * wy + s;
@@ -277,7 +323,7 @@ __global__ __launch_bounds__(512, 1) void dist_tile_kernel(DistLaunch a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t i = i0 + q;
-                    const double Ei = E[i];
+                    const double Ei = __shfl(erow[s], 8 * g + 4 * (lane >> 5) + q, 64);
                     const double r2 = fma(-2.0, (double)acc[s][u][4 * g + q], Ei + Ej) * invK;
                     const float v = sqrtf((float)fmax(r2, 0.0));
                     const bool live = i < j && j < N;
