@@ -15,8 +15,8 @@
 //               chunk layout (K-blocks of 32) and the model's contact count.
 //               Each contact is decided on d^2 = fma(u, u, fma(v, v, w w)) <
 //               cutoff^2 in FP64 from the float32 coordinates
-//  cmo_tile     256x256 pair tile per 8-wave workgroup, operand chunks staged
-//               in LDS per K-block (double-buffered), 64x128 pairs per wave;
+//  cmo_tile     256x256 pair tile per 8-wave workgroup, operand chunks
+//               streamed into a 3-slot LDS ring, 64x128 pairs per wave;
 //               epilogue S in FP64 (one correctly rounded division), packed
 //               float32 store.  Everything is exact up to that one rounding.
 #include "internal.h"
@@ -25,8 +25,6 @@ namespace clusco {
 
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void cmo_pin() { asm volatile("" ::: "memory"); }
 
 __global__ __launch_bounds__(256) void cmo_pairs_kernel(CmoLaunch a)
 {
@@ -78,11 +76,28 @@ __global__ __launch_bounds__(64) void cmo_prep_kernel(CmoLaunch a)
 constexpr int CT = 256;            // models per workgroup tile edge
 constexpr int CB = CT / ROWBLK;    // 32-model blocks per tile edge
 
+// s_waitcnt vmcnt(N) lgkmcnt(0) (expcnt left free), N <= 63.
+template <int N>
+__device__ __forceinline__ void cmo_wait_vm_lgkm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// Operand chunks go straight from global memory into a 3-slot LDS ring
+// (global_load_lds_dwordx4: load m of wave w moves chunk w + 8 m, lane l's
+// 16 bytes landing at chunk base + 16 l), three K-blocks ahead, and each wave
+// reads the next K-block's fragments into a second register set while the
+// current K-block's products run.  Step s: loads of K-block s + 3 into the
+// slot read at step s - 1, reads of slot s + 1, the products of K-block s,
+// then a wait for the loads of K-block s + 2 only and a bare barrier.  The
+// slots are separate LDS arrays in a loop unrolled by three, with the same
+// number of loads in every step, so the compiler adds no waits of its own.
 __global__ __launch_bounds__(512, 1) void cmo_tile_kernel(CmoLaunch a)
 {
     constexpr int NCH = 2 * CB;    // chunks per K-block: A then B
-    constexpr int PER = NCH / 8;   // chunk loads per thread
-    __shared__ i32x4 lds[2][NCH][64];
+    constexpr int PER = NCH / 8;   // chunk loads per wave
+    __shared__ i32x4 slot0[NCH * 64], slot1[NCH * 64], slot2[NCH * 64];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -102,13 +117,26 @@ __global__ __launch_bounds__(512, 1) void cmo_tile_kernel(CmoLaunch a)
         const int64_t R = (q < CB ? bi : bj) * CB + q % CB;
         src[m] = R * KB * 64;
     }
-    const i32x4 *opl = ops + lane;
-    i32x4 pre[PER];
+    // K-block kb into a slot; kb >= KB loads the first chunk of the operand
+    // array (present, cached) into a slot nobody reads again
+    auto dma = [&](int64_t kb, i32x4 *slot) {
 #pragma unroll
-    for (int m = 0; m < PER; ++m) pre[m] = opl[src[m]];
+        for (int m = 0; m < PER; ++m) {
+            const i32x4 *g = (kb < KB ? ops + src[m] + kb * 64 : ops) + lane;
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                             (void __attribute__((address_space(3))) *)(slot + (w + 8 * m) * 64),
+                                             16, 0, 0);
+        }
+    };
+    struct Frag {
+        i32x4 A[2], B[4];
+    };
+    auto read = [&](const i32x4 *slot, Frag &f) {
 #pragma unroll
-    for (int m = 0; m < PER; ++m) lds[0][w + 8 * m][lane] = pre[m];
-    __syncthreads();
+        for (int s = 0; s < 2; ++s) f.A[s] = slot[(2 * wy + s) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f.B[u] = slot[(CB + 4 * wx + u) * 64 + lane];
+    };
 
     i32x16 acc[2][4];
 #pragma unroll
@@ -117,43 +145,59 @@ __global__ __launch_bounds__(512, 1) void cmo_tile_kernel(CmoLaunch a)
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[s][u][r] = 0;
-
-    for (int64_t kb = 0; kb < KB; ++kb) {
-        const int buf = (int)(kb & 1);
-        const bool more = kb + 1 < KB;
-        if (more) {
+    Frag cur;
+    auto step = [&](int64_t s, i32x4 *sd, const i32x4 *sr) {
+        dma(s + 3, sd);
+        Frag nxt;
+        read(sr, nxt);
 #pragma unroll
-            for (int m = 0; m < PER; ++m) pre[m] = opl[src[m] + (kb + 1) * 64];
-        }
-        cmo_pin();
-        i32x4 A[2], B[4];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) A[s] = lds[buf][2 * wy + s][lane];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) B[u] = lds[buf][CB + 4 * wx + u][lane];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int si = 0; si < 2; ++si)
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                acc[s][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B[u], acc[s][u], 0, 0, 0);
-        if (more) {
-#pragma unroll
-            for (int m = 0; m < PER; ++m) lds[buf ^ 1][w + 8 * m][lane] = pre[m];
-        }
-        __syncthreads();
+                acc[si][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(cur.A[si], cur.B[u], acc[si][u], 0, 0, 0);
+        // the loads of K-block s + 2 have landed (those of s + 3 stay in
+        // flight) and this wave's reads of slot s + 1 are done before another
+        // wave's loads may overwrite it
+        __builtin_amdgcn_sched_barrier(0);
+        cmo_wait_vm_lgkm<PER>();
+        __builtin_amdgcn_s_barrier();
+        cur = nxt;
+    };
+
+    dma(0, slot0);
+    dma(1, slot1);
+    dma(2, slot2);
+    cmo_wait_vm_lgkm<PER>();       // K-blocks 0 and 1 have landed
+    __builtin_amdgcn_s_barrier();
+    read(slot0, cur);
+    int64_t s = 0;
+    for (; s + 3 <= KB; s += 3) {
+        step(s, slot0, slot1);
+        step(s + 1, slot1, slot2);
+        step(s + 2, slot2, slot0);
     }
+    if (s < KB) step(s, slot0, slot1);
+    if (s + 1 < KB) step(s + 1, slot1, slot2);
+    cmo_wait_vm_lgkm<0>();         // no load into LDS outlives the workgroup
     if (idle) return;
 
-    // epilogue: lane holds column j = lane%32, rows 8(r/4) + 4(lane/32) + r%4
+    // epilogue: lane holds column j = lane%32, rows 8(r/4) + 4(lane/32) + r%4;
+    // contact counts of the wave's 64 rows (two per lane, shuffled to each
+    // pair) and its lane's four columns, in one batch of loads
     const int *cnt = (const int *)(a.ws + a.off_n);
     const int64_t N = a.N;
+    int nrow[2], ncol[4];
+#pragma unroll
+    for (int si = 0; si < 2; ++si) nrow[si] = cnt[(bi * CB + 2 * wy + si) * ROWBLK + (lane & 31)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ncol[u] = cnt[(bj * CB + 4 * wx + u) * ROWBLK + (lane & 31)];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int64_t j = (bj * CB + 4 * wx + u) * ROWBLK + (lane & 31);
-        const int nj = cnt[j];
+        const int nj = ncol[u];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int64_t R = bi * CB + 2 * wy + s;
+        for (int si = 0; si < 2; ++si) {
+            const int64_t R = bi * CB + 2 * wy + si;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int64_t i0 = R * ROWBLK + 8 * g + 4 * (lane >> 5);
@@ -161,8 +205,8 @@ __global__ __launch_bounds__(512, 1) void cmo_tile_kernel(CmoLaunch a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t i = i0 + q;
-                    const int den = cnt[i] + nj;
-                    const double sc = den > 0 ? (200.0 * (double)acc[s][u][4 * g + q]) / (double)den : 0.0;
+                    const int den = __shfl(nrow[si], 8 * g + 4 * (lane >> 5) + q, 64) + nj;
+                    const double sc = den > 0 ? (200.0 * (double)acc[si][u][4 * g + q]) / (double)den : 0.0;
                     if (i < j && j < N) a.out[base + j] = (float)sc;
                     base += N - i - 2;
                 }
