@@ -72,59 +72,92 @@ __device__ __forceinline__ uint16_t bf16_rn(float f)
     return (uint16_t)(u >> 16);
 }
 
-// One wave per padded model: e_m = d_m - c into the operand layout.
+// e_m = d_m - c into the operand layout, one workgroup of PREP_T threads per
+// row block of 32 padded models.  Thread (slot, kq) builds the 16 bytes of
+// lane slot = r + 32 h of K-block kb = PREP_G i + kq (every i): the EL consecutive
+// distance indices kb*KBW + EL h + el of model r, rounded to the operand
+// format (FP32; or hi and lo halves in bf16 / fp16, both chunks), so each
+// wave writes whole 1 KiB chunks.  E_m is summed from the same rounded
+// values per thread, then over the model's 2 PREP_G threads in a fixed order.
+constexpr int PREP_T = 1024;
+constexpr int PREP_G = PREP_T / 64;   // K-block groups per workgroup
+
 template <int MODE>
-__global__ __launch_bounds__(64) void dist_prep_kernel(DistLaunch a)
+__global__ __launch_bounds__(PREP_T) void dist_prep_kernel(DistLaunch a)
 {
-    const int64_t m = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (m == 0 && lane < 2) a.counters[lane] = 0;
+    constexpr int KBW = MODE == MODE_FP32 ? 8 : 16;   // K-block width
+    constexpr int EL = KBW / 2;                       // elements per lane slot
+    __shared__ double red[PREP_T];
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid < 2) a.counters[tid] = 0;
+    const int64_t R = blockIdx.x;
+    const int slot = tid & 63, kq = tid >> 6;
+    const int r = slot & 31, h = slot >> 5;
+    const int64_t m = R * ROWBLK + r;
     const bool real = m < a.N;
     const float *x = a.X + (real ? m : 0) * a.L * 3;
     const double *c = (const double *)(a.ws + a.off_c);
     const uint32_t *pq = (const uint32_t *)(a.ws + a.off_pq);
-    double *E = (double *)(a.ws + a.off_E);
-    const int64_t R = m / ROWBLK;
-    const int r = (int)(m % ROWBLK);
     double e = 0.0;
-    for (int64_t k = lane; k < a.Kp; k += 64) {
-        double v = 0.0;
-        if (real && k < a.K) {
-            const uint32_t t = pq[k];
-            v = dist64(x, (int)(t & 0xFFFFu), (int)(t >> 16)) - c[k];
+    for (int64_t kb = kq; kb < a.KB; kb += PREP_G) {
+        const int64_t k0 = kb * KBW + EL * h;
+        double v[EL];
+#pragma unroll
+        for (int el = 0; el < EL; ++el) {
+            const int64_t k = k0 + el;
+            v[el] = 0.0;
+            if (real && k < a.K) {
+                const uint32_t t = pq[k];
+                v[el] = dist64(x, (int)(t & 0xFFFFu), (int)(t >> 16)) - c[k];
+            }
         }
         if constexpr (MODE == MODE_FP32) {
-            const float f = (float)v;
-            e += (double)f * (double)f;
-            const int64_t kb = k >> 3, h = (k >> 2) & 1, el = k & 3;
-            ((float *)(a.ws + a.off_ops))[((R * a.KB + kb) * 64 + r + 32 * h) * 4 + el] = f;
-        } else {
-            const int64_t kb = k >> 4, h = (k >> 3) & 1, el = k & 7;
-            const int64_t base = ((R * a.KB + kb) * 2) * 64;
-            uint16_t *ops = (uint16_t *)(a.ws + a.off_ops);
-            double hv, lv;
-            uint16_t hb, lb;
-            if constexpr (is_bf16(MODE)) {
-                hb = bf16_rn((float)v);
-                hv = (double)__uint_as_float((uint32_t)hb << 16);
-                lb = bf16_rn((float)(v - hv));
-                lv = (double)__uint_as_float((uint32_t)lb << 16);
-            } else {
-                const _Float16 hh = (_Float16)(float)v;
-                hv = (double)(float)hh;
-                const _Float16 ll = (_Float16)(float)(v - hv);
-                lv = (double)(float)ll;
-                hb = __builtin_bit_cast(uint16_t, hh);
-                lb = __builtin_bit_cast(uint16_t, ll);
+            f32x4 f;
+#pragma unroll
+            for (int el = 0; el < EL; ++el) {
+                f[el] = (float)v[el];
+                e += (double)f[el] * (double)f[el];
             }
-            ops[(base + r + 32 * h) * 8 + el] = hb;
-            ops[(base + 64 + r + 32 * h) * 8 + el] = lb;
-            const double sv = hv + lv;
-            e += sv * sv;
+            ((f32x4 *)(a.ws + a.off_ops))[(R * a.KB + kb) * 64 + slot] = f;
+        } else {
+            uint16_t hb[EL], lb[EL];
+#pragma unroll
+            for (int el = 0; el < EL; ++el) {
+                double hv, lv;
+                if constexpr (is_bf16(MODE)) {
+                    hb[el] = bf16_rn((float)v[el]);
+                    hv = (double)__uint_as_float((uint32_t)hb[el] << 16);
+                    lb[el] = bf16_rn((float)(v[el] - hv));
+                    lv = (double)__uint_as_float((uint32_t)lb[el] << 16);
+                } else {
+                    const _Float16 hh = (_Float16)(float)v[el];
+                    hv = (double)(float)hh;
+                    const _Float16 ll = (_Float16)(float)(v[el] - hv);
+                    lv = (double)(float)ll;
+                    hb[el] = __builtin_bit_cast(uint16_t, hh);
+                    lb[el] = __builtin_bit_cast(uint16_t, ll);
+                }
+                const double sv = hv + lv;
+                e += sv * sv;
+            }
+            u32x4 hw, lw;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                hw[q] = (uint32_t)hb[2 * q] | ((uint32_t)hb[2 * q + 1] << 16);
+                lw[q] = (uint32_t)lb[2 * q] | ((uint32_t)lb[2 * q + 1] << 16);
+            }
+            u32x4 *ops = (u32x4 *)(a.ws + a.off_ops) + (R * a.KB + kb) * 2 * 64;
+            ops[slot] = hw;
+            ops[64 + slot] = lw;
         }
     }
-    e = wave_sum64(e);
-    if (lane == 0) E[m] = e;
+    red[tid] = e;
+    __syncthreads();
+    if (tid < ROWBLK) {
+        double sum = 0.0;
+        for (int q = 0; q < 2 * PREP_G; ++q) sum += red[tid + 32 * q];   // h = q & 1, kq = q >> 1
+        ((double *)(a.ws + a.off_E))[R * ROWBLK + tid] = sum;
+    }
 }
 
 template <int MODE>
@@ -391,7 +424,7 @@ hipError_t launch_dist_prep(int mode, const DistLaunch &a, hipStream_t s)
     dist_ref_kernel<<<dim3((unsigned)((a.Kp + 255) / 256)), dim3(256), 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == MODE_FP64) return e;   // FP64: the fix-up does all
-    const dim3 pg((unsigned)a.Np), pb(64);
+    const dim3 pg((unsigned)(a.Np / ROWBLK)), pb(PREP_T);
     switch (mode) {
     case MODE_FP32: dist_prep_kernel<MODE_FP32><<<pg, pb, 0, s>>>(a); break;
     case MODE_FP16: dist_prep_kernel<MODE_FP16><<<pg, pb, 0, s>>>(a); break;

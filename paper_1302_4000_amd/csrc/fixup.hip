@@ -6,7 +6,7 @@
 // below flag_coef (E_i + E_j); this kernel re-evaluates that test on the
 // stored scores of each listed block, compacts the flagged pairs in LDS and
 // recomputes each one from the raw float32 coordinates entirely in FP64
-// (see pair_fp64_span), then the same Eq. 2 epilogue.  With `all` set (FP64 precision) every pair
+// (see pair_corr_span and pair_score), then the same Eq. 2 epilogue.  With `all` set (FP64 precision) every pair
 // of every block is computed this way.  In threshold mode the candidates are
 // the pairs the tile kernel marked in the block's ownership mask, and the
 // recomputed pairs below the cutoff are appended to the output arrays.
@@ -15,21 +15,18 @@
 
 namespace clusco {
 
-// cRMSD of one pair entirely in FP64 from the raw float32 coordinates:
-// H = sum_l x_l y_l^T - L c_x c_y^T (the centred correlation; in FP64 the
-// cancellation against translations of ~100 A costs about one digit) and
-// the exact FP64 radii computed once per model by the prep pass.  The atoms
-// are split over FIX_SPAN lanes (lane sl takes atoms sl, sl + FIX_SPAN, ...:
-// consecutive lanes read consecutive atoms), the partial correlations summed
-// by a fixed xor butterfly (reproducible); every lane of the group then
-// holds the whole H and runs the epilogue.
+// Correlation of one pair entirely in FP64 from the raw float32 coordinates,
+// H = sum_l x_l y_l^T (centred in pair_score), with the atoms split over
+// FIX_SPAN lanes (lane sl takes atoms sl, sl + FIX_SPAN, ...: consecutive
+// lanes read consecutive atoms) and the partial sums added by a fixed xor
+// butterfly (reproducible); every lane of the group ends with the whole H.
 constexpr int FIX_SPAN = 16;
 
-__device__ __forceinline__ float pair_fp64_span(const float *xi, const float *xj, const double *ci,
-                                                const double *cj, double ea, double eb, int64_t L,
-                                                int sl)
+__device__ __forceinline__ void pair_corr_span(const float *xi, const float *xj, int64_t L, int sl,
+                                               double h[9])
 {
-    double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 9; ++u) h[u] = 0.0;
     for (int64_t l = sl; l < L; l += FIX_SPAN) {
         double a[3], b[3];
 #pragma unroll
@@ -46,6 +43,14 @@ __device__ __forceinline__ float pair_fp64_span(const float *xi, const float *xj
     for (int off = FIX_SPAN / 2; off > 0; off >>= 1)
 #pragma unroll
         for (int u = 0; u < 9; ++u) h[u] += __shfl_xor(h[u], off, FIX_SPAN);
+}
+
+// cRMSD from the uncentred correlation: H - L c_x c_y^T (the centred
+// correlation; in FP64 the cancellation against translations of ~100 A costs
+// about one digit) and the exact FP64 radii computed once per model by prep.
+__device__ __forceinline__ float pair_score(double h[9], const double *ci, const double *cj,
+                                            double ea, double eb, int64_t L)
+{
     const double dl = (double)L;
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -57,11 +62,11 @@ __device__ __forceinline__ float pair_fp64_span(const float *xi, const float *xj
 
 // One workgroup of FIX_THREADS per listed block at a time.
 constexpr int FIX_THREADS = 256;
-constexpr int FIX_PAIRS = FIX_THREADS / FIX_SPAN;   // pairs in flight per workgroup
 
 __global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
 {
     __shared__ uint16_t todo[ROWBLK * ROWBLK];
+    __shared__ double hbuf[9][FIX_THREADS];
     __shared__ int cnt;
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t n = a.all ? a.n_all : (int64_t)a.counters[0];
@@ -116,21 +121,43 @@ __global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
         const double *cenB = (const double *)(a.ws + p.cenB);
         const double *E64A = (const double *)(a.ws + p.E64A);
         const double *E64B = (const double *)(a.ws + p.E64B);
-        const int ps = tid / FIX_SPAN, sl = tid % FIX_SPAN;
-        for (int s0 = 0; s0 < m; s0 += FIX_PAIRS) {   // uniform trip count (ballots below)
-            const int s = s0 + ps;
+        // per round of FIX_THREADS pairs: FIX_SPAN passes in which each
+        // group of FIX_SPAN lanes computes one pair's correlation (all
+        // groups at once) and parks it in LDS; then every thread finishes
+        // one pair (one epilogue per pair, not one per lane of a group)
+        const int grp = tid / FIX_SPAN, sl = tid % FIX_SPAN;
+        for (int s0 = 0; s0 < m; s0 += FIX_THREADS) {   // uniform trip count (ballots below)
+#pragma unroll 1
+            for (int pass = 0; pass < FIX_SPAN; ++pass) {
+                const int sp = s0 + pass * (FIX_THREADS / FIX_SPAN) + grp;
+                if (sp < m) {     // uniform over each group of FIX_SPAN lanes
+                    const int q = todo[sp];
+                    const int64_t ip = Ra * ROWBLK + (q >> 5), jp = Rb * ROWBLK + (q & 31);
+                    double h[9];
+                    pair_corr_span(XA + ip * L * 3, XB + jp * L * 3, L, sl, h);
+                    if (sl == 0) {
+#pragma unroll
+                        for (int u = 0; u < 9; ++u) hbuf[u][sp - s0] = h[u];
+                    }
+                }
+            }
+            __syncthreads();
+            const int s = s0 + tid;
             int64_t i = 0, j = 0;
             float v = 0.0f;
-            if (s < m) {          // uniform over each group of FIX_SPAN lanes
+            if (s < m) {
                 const int q = todo[s];
                 i = Ra * ROWBLK + (q >> 5);
                 j = Rb * ROWBLK + (q & 31);
-                v = pair_fp64_span(XA + i * L * 3, XB + j * L * 3, cenA + 3 * i, cenB + 3 * j,
-                                   E64A[i], E64B[j], L, sl);
-                if (!a.thr && sl == 0) out[p.sym ? packed_index(i, j, NA) : i * NB + j] = v;
+                double h[9];
+#pragma unroll
+                for (int u = 0; u < 9; ++u) h[u] = hbuf[u][tid];
+                v = pair_score(h, cenA + 3 * i, cenB + 3 * j, E64A[i], E64B[j], L);
+                if (!a.thr) out[p.sym ? packed_index(i, j, NA) : i * NB + j] = v;
             }
+            __syncthreads();      // hbuf is rewritten by the next round
             if (a.thr) {
-                const bool em = s < m && sl == 0 && v < (float)a.emit.cutoff;
+                const bool em = s < m && v < (float)a.emit.cutoff;
                 const unsigned long long b = __ballot(em);
                 if (b) {
                     unsigned long long base = 0;
