@@ -20,7 +20,7 @@ namespace clusco {
 // FIX_SPAN lanes (lane sl takes atoms sl, sl + FIX_SPAN, ...: consecutive
 // lanes read consecutive atoms) and the partial sums added by a fixed xor
 // butterfly (reproducible); every lane of the group ends with the whole H.
-constexpr int FIX_SPAN = 16;
+constexpr int FIX_SPAN = 8;
 
 __device__ __forceinline__ void pair_corr_span(const float *xi, const float *xj, int64_t L, int sl,
                                                double h[9])
