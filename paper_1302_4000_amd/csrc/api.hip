@@ -937,7 +937,7 @@ clusco_status clusco_crmsd_threshold(clusco_handle h, const float *coords, int64
     fl.prob = t.s.p;
     fl.nprob = 1;
     fl.counters = (int *)w;
-    fl.list = (const FixEntry *)(w + t.s.off_list);
+    fl.list = (FixEntry *)(w + t.s.off_list);
     fl.thr = 1;
     fl.emit = em;
     if (mode != MODE_FP64) {

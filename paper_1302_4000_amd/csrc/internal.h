@@ -256,7 +256,7 @@ struct FixupLaunch {
     int32_t all;          // 1: recompute every pair of every block (FP64 precision)
     int64_t n_all;        // 32x32 blocks in the launch when all = 1
     const int *counters;
-    const FixEntry *list;
+    FixEntry *list;       // the dense fix-up marks the entries it takes
     int32_t thr;          // 1: emit pairs below emit.cutoff instead of storing scores
     int32_t pad;
     Emit emit;
