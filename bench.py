@@ -392,7 +392,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and backward measurements")
-    ap.add_argument("--leg", choices=["backward"], default=None,
+    ap.add_argument("--leg", choices=["backward", "batched"], default=None,
                     help="only run one supporting measurement and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter scaling)")
@@ -416,6 +416,10 @@ def main():
     if args.leg == "backward":
         log("[bench] backward only: N=4096 L=256")
         print(json.dumps({"leg": "backward", **backward_leg(cl, torch, args.steps)}), flush=True)
+        return
+    if args.leg == "batched":
+        log("[bench] batched only: 64 uneven ensembles")
+        print(json.dumps({"leg": "batched", **batched_leg(cl, torch, args.steps)}), flush=True)
         return
 
     log(f"[bench] generating {args.workload}")
