@@ -88,8 +88,27 @@ constexpr int KT = 64;   // pair tile edge of the cost pass
 // registers while the tile row is unchanged; the wave reduces them and one
 // 64-bit atomic per row reaches HBM when the run leaves the row.  Column sums
 // are combined over the four waves in LDS, one atomic per column and tile.
-// (Atomics across the XCDs are the expensive part: one per scattered pair
-// instead of one per column and tile is several times slower.)
+// The next tile's 16 scores per thread are loaded while the current tile is
+// summed, and the labels of a wave's 16 rows are loaded once per tile row, so
+// a tile waits on no load of its own.  (Atomics across the XCDs are the
+// expensive part of a scattered design: one per scattered pair instead of one
+// per column and tile is several times slower.)
+__device__ __forceinline__ void cost_tile_load(const ClusterLaunch &a, int N, int64_t bi, int64_t bj,
+                                               int g, int lane, float (&d)[16], int &lj)
+{
+    const int j = (int)(bj * KT) + lane;
+    const int i0 = (int)(bi * KT) + g * 16;
+    lj = j < N ? a.label[j] : -1;
+    // packed row starts advance by N - i - 2
+    int64_t base = (int64_t)i0 * (2 * (int64_t)N - i0 - 1) / 2 - i0 - 1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + r;
+        d[r] = (i < j && j < N) ? a.D[base + j] : 0.0f;
+        base += N - i - 2;
+    }
+}
+
 __global__ __launch_bounds__(256) void km_cost(ClusterLaunch a, int final)
 {
     const int *st = a.state;
@@ -98,46 +117,51 @@ __global__ __launch_bounds__(256) void km_cost(ClusterLaunch a, int final)
     const int64_t nt = (a.N + KT - 1) / KT;
     const int64_t T = tri_count(nt);
     const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
+    if (t0 >= t1) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63, g = tid >> 6;
     const int N = (int)a.N;                     // N <= 2^20: indices fit 32 bits
     unsigned long long racc[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) racc[r] = 0;
-    int64_t bi = -1, bj = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        if (bi < 0) {
-            tri_decode(t, nt, &bi, &bj);
-        } else if (++bj == nt) {               // next tile row: flush the row sums
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const unsigned long long v = wave_sum_u64(racc[r]);
-                racc[r] = 0;
-                if (lane == 0 && v != 0)
-                    atomicAdd((unsigned long long *)&a.cost[bi * KT + g * 16 + r], v);
-            }
-            ++bi;
-            bj = bi;
-        }
-        const int j = (int)(bj * KT) + lane;
-        const int i0 = (int)(bi * KT) + g * 16;
-        const int lj = j < N ? a.label[j] : -1;
-        // all 16 scores of this thread's column first (independent loads in
-        // flight), then the label tests; packed row starts advance by N - i - 2
-        float d[16];
-        int64_t base = (int64_t)i0 * (2 * (int64_t)N - i0 - 1) / 2 - i0 - 1;
+    int64_t bi, bj;
+    tri_decode(t0, nt, &bi, &bj);
+    float d[16];
+    int lj, lab[16];
+    cost_tile_load(a, N, bi, bj, g, lane, d, lj);
+    auto row_labels = [&](int64_t b) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int i = i0 + r;
-            d[r] = (i < j && j < N) ? a.D[base + j] : 0.0f;
-            base += N - i - 2;
+            const int64_t i = b * KT + g * 16 + r;
+            lab[r] = i < N ? a.label[i] : -2;
         }
+    };
+    auto row_flush = [&](int64_t b) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const unsigned long long v = wave_sum_u64(racc[r]);
+            racc[r] = 0;
+            if (lane == 0 && v != 0) atomicAdd((unsigned long long *)&a.cost[b * KT + g * 16 + r], v);
+        }
+    };
+    row_labels(bi);
+    for (int64_t t = t0; t < t1; ++t) {
+        int64_t ni = bi, nj = bj + 1;
+        if (nj == nt) {
+            ni = bi + 1;
+            nj = ni;
+        }
+        float dn[16];
+        int ljn = -1;
+        if (t + 1 < t1) cost_tile_load(a, N, ni, nj, g, lane, dn, ljn);
+        const int j = (int)(bj * KT) + lane;
+        const int i0 = (int)(bi * KT) + g * 16;
         unsigned long long cs = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int i = i0 + r;
             const unsigned long long q =
-                (i < j && j < N && a.label[i] == lj) ? (unsigned long long)quant(d[r]) : 0ull;
+                (i < j && j < N && lab[r] == lj) ? (unsigned long long)quant(d[r]) : 0ull;
             cs += q;
             racc[r] += q;
         }
@@ -148,15 +172,19 @@ __global__ __launch_bounds__(256) void km_cost(ClusterLaunch a, int final)
             if (c != 0) atomicAdd((unsigned long long *)&a.cost[bj * KT + tid], c);
         }
         __syncthreads();
-    }
-    if (bi >= 0) {
+        if (t + 1 < t1) {
+            if (ni != bi) {                     // next tile row: flush the row sums
+                row_flush(bi);
+                row_labels(ni);
+            }
+            bi = ni;
+            bj = nj;
+            lj = ljn;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const unsigned long long v = wave_sum_u64(racc[r]);
-            if (lane == 0 && v != 0)
-                atomicAdd((unsigned long long *)&a.cost[bi * KT + g * 16 + r], v);
+            for (int r = 0; r < 16; ++r) d[r] = dn[r];
         }
     }
+    row_flush(bi);
 }
 
 // Block-wide lexicographic minimum of (key, index) over 256 threads.
