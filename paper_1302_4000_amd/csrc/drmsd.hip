@@ -82,12 +82,18 @@ __device__ __forceinline__ uint16_t bf16_rn(float f)
 constexpr int PREP_T = 1024;
 constexpr int PREP_G = PREP_T / 64;   // K-block groups per workgroup
 
-template <int MODE>
+// Models of up to PREP_LDS_L atoms: the row block's 32 models are staged in
+// LDS first (coalesced), so the six coordinates of each distance come from
+// LDS instead of scattered cached global loads.
+constexpr int PREP_LDS_L = 160;
+
+template <int MODE, bool XL>
 __global__ __launch_bounds__(PREP_T) void dist_prep_kernel(DistLaunch a)
 {
     constexpr int KBW = MODE == MODE_FP32 ? 8 : 16;   // K-block width
     constexpr int EL = KBW / 2;                       // elements per lane slot
     __shared__ double red[PREP_T];
+    __shared__ float xs[XL ? ROWBLK * PREP_LDS_L * 3 : 1];
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid < 2) a.counters[tid] = 0;
     const int64_t R = blockIdx.x;
@@ -95,7 +101,18 @@ __global__ __launch_bounds__(PREP_T) void dist_prep_kernel(DistLaunch a)
     const int r = slot & 31, h = slot >> 5;
     const int64_t m = R * ROWBLK + r;
     const bool real = m < a.N;
-    const float *x = a.X + (real ? m : 0) * a.L * 3;
+    const float *x;
+    if constexpr (XL) {
+        // the row block's models are contiguous: [R*32, R*32 + nr) x L x 3
+        const int64_t nr = a.N - R * ROWBLK < ROWBLK ? a.N - R * ROWBLK : ROWBLK;
+        const int64_t nf = (nr > 0 ? nr : 0) * a.L * 3;
+        const float *src = a.X + R * ROWBLK * a.L * 3;
+        for (int64_t f = tid; f < nf; f += PREP_T) xs[f] = src[f];
+        __syncthreads();
+        x = xs + (real ? r : 0) * a.L * 3;
+    } else {
+        x = a.X + (real ? m : 0) * a.L * 3;
+    }
     const double *c = (const double *)(a.ws + a.off_c);
     const uint32_t *pq = (const uint32_t *)(a.ws + a.off_pq);
     double e = 0.0;
@@ -425,11 +442,21 @@ hipError_t launch_dist_prep(int mode, const DistLaunch &a, hipStream_t s)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == MODE_FP64) return e;   // FP64: the fix-up does all
     const dim3 pg((unsigned)(a.Np / ROWBLK)), pb(PREP_T);
+    const bool xl = a.L <= PREP_LDS_L;
     switch (mode) {
-    case MODE_FP32: dist_prep_kernel<MODE_FP32><<<pg, pb, 0, s>>>(a); break;
-    case MODE_FP16: dist_prep_kernel<MODE_FP16><<<pg, pb, 0, s>>>(a); break;
+    case MODE_FP32:
+        if (xl) dist_prep_kernel<MODE_FP32, true><<<pg, pb, 0, s>>>(a);
+        else dist_prep_kernel<MODE_FP32, false><<<pg, pb, 0, s>>>(a);
+        break;
+    case MODE_FP16:
+        if (xl) dist_prep_kernel<MODE_FP16, true><<<pg, pb, 0, s>>>(a);
+        else dist_prep_kernel<MODE_FP16, false><<<pg, pb, 0, s>>>(a);
+        break;
     case MODE_BF16:
-    case MODE_BF16X4: dist_prep_kernel<MODE_BF16><<<pg, pb, 0, s>>>(a); break;
+    case MODE_BF16X4:
+        if (xl) dist_prep_kernel<MODE_BF16, true><<<pg, pb, 0, s>>>(a);
+        else dist_prep_kernel<MODE_BF16, false><<<pg, pb, 0, s>>>(a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
