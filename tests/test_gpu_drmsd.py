@@ -47,7 +47,8 @@ def test_n300_l60_all_pairs(cl, prec):
 
 
 @pytest.mark.parametrize("N,L", [(2, 2), (3, 3), (5, 7), (33, 17), (65, 33), (77, 5),
-                                 (129, 64), (130, 100), (257, 23)])
+                                 (129, 64), (130, 100), (257, 23), (40, 160), (37, 161),
+                                 (70, 230)])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_ragged_shapes(cl, N, L, prec):
     say(f"[drmsd] ragged N={N} L={L} {prec}")
