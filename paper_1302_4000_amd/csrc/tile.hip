@@ -335,12 +335,20 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long b)
 
 // Threshold epilogue: scores as in the forward epilogue, but instead of the
 // packed store, pairs below the cutoff are appended to the output arrays
-// (one atomic per wave for the whole 32x32 block, then each lane writes at
-// its prefix position).  Pairs the fix-up will recompute are not emitted
-// here; their bits go into the block's ownership mask with the list entry.
-__device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem &p,
-                                             const WaveJob &job, int lane, const f32x16 acc[9],
-                                             const EpiRadii &er)
+// (one atomic for the whole 32x32 block, or for the workgroup's four blocks
+// in the staged kernel, then each lane writes at its prefix position).  Pairs
+// the fix-up will recompute are not emitted here; their bits go into the
+// block's ownership mask with the list entry.  thr_scores does everything up
+// to the count of the wave's pairs to emit; thr_write appends them at base.
+struct ThrPairs {
+    float vs[16];
+    uint32_t emit;
+    uint32_t total;   // pairs of the wave to emit
+};
+
+__device__ __forceinline__ void thr_scores(const TileLaunch &a, const Problem &p, const WaveJob &job,
+                                           int lane, const f32x16 acc[9], const EpiRadii &er,
+                                           ThrPairs &tp)
 {
     const int64_t NA = p.NA;
     const double invL = 1.0 / (double)p.L;
@@ -349,7 +357,6 @@ __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem 
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
     const double Ej = er.ej;
     const bool jlive = j < NA;
-    float vs[16];
     uint32_t emit = 0, flag = 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -364,7 +371,7 @@ __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem 
         const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[0] * invL, 0.0));
         const bool live = jlive && i < j;
         const bool fl = live && (double)v < coef * (Ei + Ej);
-        vs[r] = v;
+        tp.vs[r] = v;
         flag |= (uint32_t)fl << r;
         emit |= (uint32_t)(live && !fl && v < cutoff) << r;
     }
@@ -388,24 +395,42 @@ __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem 
     uint32_t total = 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) total += (uint32_t)__popcll(__ballot((emit >> r) & 1u));
-    if (total == 0) return;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(a.emit.count, (unsigned long long)total);
-    base = __shfl(base, 0, 64);
+    tp.emit = emit;
+    tp.total = total;
+}
+
+__device__ __forceinline__ void thr_write(const TileLaunch &a, const WaveJob &job, int lane,
+                                          const ThrPairs &tp, unsigned long long base)
+{
+    const int64_t j = job.Rb * ROWBLK + (lane & 31);
     unsigned long long off = 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const unsigned long long b = __ballot((emit >> r) & 1u);
-        if ((emit >> r) & 1u) {
+        const unsigned long long b = __ballot((tp.emit >> r) & 1u);
+        if ((tp.emit >> r) & 1u) {
             const unsigned long long pos = base + off + lanes_below(b);
             if (pos < (unsigned long long)a.emit.capacity) {
                 a.emit.i[pos] = (int32_t)(job.Ra * ROWBLK + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
                 a.emit.j[pos] = (int32_t)j;
-                a.emit.score[pos] = vs[r];
+                a.emit.score[pos] = tp.vs[r];
             }
         }
         off += (unsigned long long)__popcll(b);
     }
+}
+
+// One wave's block on its own: one atomic per wave.
+__device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem &p,
+                                             const WaveJob &job, int lane, const f32x16 acc[9],
+                                             const EpiRadii &er)
+{
+    ThrPairs tp;
+    thr_scores(a, p, job, lane, acc, er, tp);
+    if (tp.total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.emit.count, (unsigned long long)tp.total);
+    base = __shfl(base, 0, 64);
+    thr_write(a, job, lane, tp, base);
 }
 
 // Persistent ping-pong kernel.  A workgroup is two groups of four waves, one
@@ -668,9 +693,28 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     wait_vmcnt<0>();    // no load into LDS outlives the workgroup
     __builtin_amdgcn_s_setprio(0);
 
-    if (job.active) {
+    if constexpr (OP == OP_THR) {
+        // the four waves' emission counts go to the output counter in one
+        // atomic per workgroup (every wave, active or not, meets the barriers)
+        __shared__ uint32_t wtot[4];
+        __shared__ unsigned long long wbase;
+        ThrPairs tp;
+        tp.total = 0;
+        if (job.active) thr_scores(a, p, job, lane, acc, er, tp);
+        if (lane == 0) wtot[w] = tp.total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t sum = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+            wbase = sum ? atomicAdd(a.emit.count, (unsigned long long)sum) : 0ull;
+        }
+        __syncthreads();
+        if (tp.total) {
+            unsigned long long base = wbase;
+            for (int v = 0; v < w; ++v) base += wtot[v];
+            thr_write(a, job, lane, tp, base);
+        }
+    } else if (job.active) {
         if constexpr (OP == OP_BWD) bwd_epilogue(a, p, job, lane, acc, er);
-        else if constexpr (OP == OP_THR) thr_epilogue(a, p, job, lane, acc, er);
         else epilogue(a, p, job, lane, acc, er);
     }
 }
