@@ -103,6 +103,39 @@ def time_path(cl, torch, x, prec, steps, warmup):
                 fixup_ms=stage_ms[2] / steps, fixup_blocks=cl.fixup_count(ws)), out
 
 
+BINS = [(0.0, 0.5), (0.5, 2.0), (2.0, 5.0), (5.0, 1e30)]
+
+
+def error_bins(d, r):
+    """Max and p99 of |error| per oracle-score bin."""
+    import numpy as np
+    res = {}
+    for lo, hi in BINS:
+        m = (r >= lo) & (r < hi)
+        key = f"{lo:g}-{hi:g}A" if hi < 1e29 else f">={lo:g}A"
+        res[key] = [float(d[m].max()), float(np.quantile(d[m], 0.99))] if m.any() else [0.0, 0.0]
+    return res
+
+
+def host_cpu():
+    """What the CPU baseline ran on: model name, logical CPUs of the host,
+    CPUs this process may use, and the OpenMP thread setting."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"model": model, "nproc_host": os.cpu_count(), "cpus_allowed": allowed,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
 def oracle_leg(x_np, outs, want_cpu, threads):
     """Maximum error of GPU scores vs the FP64 oracle on a pair sample, and
     the oracle's own throughput on a bounded sample of the workload."""
@@ -122,7 +155,6 @@ def oracle_leg(x_np, outs, want_cpu, threads):
     strata = {"uniform_1e5": (I, J), "near_identical_1225": (ii, jj), "near_vs_bulk_1e4": (I2, J2)}
     refs = {name: oracle.crmsd_pairs(x_np, a, b, threads=threads)
             for name, (a, b) in strata.items()}
-    bins = [(0.0, 0.5), (0.5, 2.0), (2.0, 5.0), (5.0, 1e30)]
     errs = {}
     for prec, out in outs.items():
         e = {}
@@ -135,12 +167,7 @@ def oracle_leg(x_np, outs, want_cpu, threads):
             allerr.append(d)
             allref.append(refs[name])
         e["max"] = max(e.values())
-        d, r = np.concatenate(allerr), np.concatenate(allref)
-        e["by_bin_max_p99"] = {
-            f"{lo:g}-{hi:g}A" if hi < 1e29 else f">={lo:g}A":
-                [float(d[(r >= lo) & (r < hi)].max(initial=0.0)),
-                 float(np.quantile(d[(r >= lo) & (r < hi)], 0.99)) if ((r >= lo) & (r < hi)).any() else 0.0]
-            for lo, hi in bins}
+        e["by_bin_max_p99"] = error_bins(np.concatenate(allerr), np.concatenate(allref))
         errs[prec] = e
     cpu = None
     if want_cpu:
@@ -162,9 +189,60 @@ def oracle_leg(x_np, outs, want_cpu, threads):
         cpu = {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                "sample": f"all-vs-all of the first {n} models of the same ensemble "
                          f"({pairs} pairs, {dt:.1f} s, FP64 explicit Kabsch, OpenMP)",
+               "host": host_cpu(),
                "one_thread": {"value": n1 * (n1 - 1) / 2 / dt1, "unit": "pairs/s",
                               "sample": f"all-vs-all of the first {n1} models ({dt1:.1f} s)"}}
     return errs, cpu
+
+
+def raw_outputs(cl, torch, x, precs):
+    """Scores with the FP64 fix-up disabled (tolerance 0): the raw error of
+    the contraction + epilogue that the fix-up flag has to cover."""
+    tol = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "bf16x4": 5e-4}
+    outs = {}
+    for p in precs:
+        cl.set_tolerance(p, 0.0)
+        try:
+            outs[p + "_raw"] = cl.crmsd_matrix(x, p)
+        finally:
+            cl.set_tolerance(p, tol[p])
+    torch.cuda.synchronize()
+    return outs
+
+
+def config2_leg(cl, torch, steps, threads, with_error):
+    """The FP32 path at N=5,000, L=300 (10% unrelated folds, sigma up to
+    8 A): pairs/s of the whole call, and its error against the oracle on
+    1e5 uniform pairs, after and before the fix-up; split-BF16 beside it."""
+    import numpy as np
+
+    import oracle
+    from paper_1302_4000_amd import synth
+    x_np = synth.workload("n5000_l300")
+    N, L = x_np.shape[0], x_np.shape[1]
+    P = N * (N - 1) // 2
+    x = torch.from_numpy(x_np).cuda()
+    res = {"workload": "n5000_l300", "N": N, "L": L, "pairs": P}
+    outs = {}
+    for prec in ("fp32", "bf16"):
+        r, out = time_path(cl, torch, x, prec, steps, 2)
+        res[prec] = r
+        outs[prec] = out
+    if with_error:
+        outs.update(raw_outputs(cl, torch, x, ("fp32", "bf16")))
+        rng = np.random.default_rng(17)
+        i = rng.integers(0, N, 100000)
+        j = rng.integers(0, N, 100000)
+        k = i != j
+        I, J = np.minimum(i, j)[k], np.maximum(i, j)[k]
+        ref = oracle.crmsd_pairs(x_np, I, J, threads=threads)
+        idx = torch.from_numpy(oracle.packed_index(I, J, N)).cuda()
+        for name, out in outs.items():
+            d = np.abs(out[idx].cpu().numpy().astype(np.float64) - ref)
+            res.setdefault("max_err_A", {})[name] = {"max": float(d.max()),
+                                                     "by_bin_max_p99": error_bins(d, ref)}
+        res["error_sample"] = f"{len(I)} uniform pairs"
+    return res
 
 
 def timed(torch, fn, steps, warmup):
@@ -179,20 +257,52 @@ def timed(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def batched_leg(cl, torch, steps):
+def batched_leg(cl, torch, steps, with_error=False, threads=1):
     """64 uneven ensembles (N ~ logU[100,2000], L ~ logU[50,500]) in one
-    launch sequence, replayed from the cached graph."""
+    launch sequence, replayed from the cached graph; with_error compares a
+    per-ensemble pair sample (uniform pairs and the first and last rows)
+    with the FP64 oracle."""
+    import numpy as np
     from paper_1302_4000_amd import synth
     ens = synth.make_batch()
     b = cl.Batch([e.shape[:2] for e in ens])
     flat = b.pack([torch.from_numpy(e) for e in ens], "cuda")
     res = {"ensembles": len(ens), "pairs": b.n_out,
            "models": int(sum(e.shape[0] for e in ens))}
+    samples = []
+    if with_error:
+        rng = np.random.default_rng(19)
+        for e in ens:
+            n = e.shape[0]
+            i = rng.integers(0, n, 300)
+            j = rng.integers(0, n, 300)
+            k = i != j
+            I = np.r_[np.minimum(i, j)[k], np.zeros(n - 1, np.int64), np.arange(n - 2, -1, -1)]
+            J = np.r_[np.maximum(i, j)[k], np.arange(1, n), np.full(n - 1, n - 1)]
+            samples.append((I, J))
+    refs = None
     for prec in ("bf16", "fp32"):
         ws = torch.empty(cl.batched_workspace_size(b, prec), dtype=torch.uint8, device="cuda")
         out = torch.empty(b.n_out, dtype=torch.float32, device="cuda")
         ms = timed(torch, lambda: cl.crmsd_batched(b, flat, prec, out=out, ws=ws), steps, 2)
-        res[prec] = {"ms_per_call": ms, "pairs_per_s": b.n_out / (ms * 1e-3)}
+        r = {"ms_per_call": ms, "pairs_per_s": b.n_out / (ms * 1e-3)}
+        if with_error:
+            import oracle
+            if refs is None:
+                refs = [oracle.crmsd_pairs(e, I, J, threads=threads)
+                        for e, (I, J) in zip(ens, samples)]
+            views = b.split(out)
+            worst, allerr, allref = 0.0, [], []
+            for e, (I, J), ref, v in zip(ens, samples, refs, views):
+                got = v[torch.from_numpy(oracle.packed_index(I, J, e.shape[0])).cuda()]
+                d = np.abs(got.cpu().numpy().astype(np.float64) - ref)
+                allerr.append(d)
+                allref.append(ref)
+            d, rr = np.concatenate(allerr), np.concatenate(allref)
+            r["max_err_A"] = {"max": float(d.max()), "by_bin_max_p99": error_bins(d, rr)}
+            r["error_sample"] = (f"{len(d)} pairs: per ensemble ~300 uniform pairs plus its "
+                                 "first and last rows")
+        res[prec] = r
     return res
 
 
@@ -434,6 +544,9 @@ def main():
     main_res, main_out = time_path(cl, torch, x, prec, args.steps, args.warmup)
     log(f"[bench] {prec}: {main_res}")
     outs = {prec: main_out}
+    if not args.no_error:
+        outs.update(raw_outputs(cl, torch, x, [prec] + ([] if args.no_compare or prec == "fp32"
+                                                        else ["fp32"])))
     cmp = None
     if not args.no_compare and prec != "fp32":
         steps = max(2, args.steps // 3)
@@ -457,13 +570,20 @@ def main():
             variants[vp] = vres
             outs[vp] = vout
 
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
     extra = {}
     if not args.no_extra:
+        log("[bench] config n5000_l300 (FP32 path at scale)")
+        extra["n5000_l300"] = config2_leg(cl, torch, max(3, args.steps // 2), threads,
+                                          not args.no_error)
+        log(f"[bench] n5000_l300: {extra['n5000_l300']}")
         log("[bench] threshold 3.2 A")
         extra["threshold"] = threshold_leg(cl, torch, x, max(3, args.steps // 2))
         log(f"[bench] threshold: {extra['threshold']}")
         log("[bench] batched: 64 uneven ensembles")
-        extra["batched"] = batched_leg(cl, torch, max(3, args.steps // 2))
+        extra["batched"] = batched_leg(cl, torch, max(3, args.steps // 2), not args.no_error,
+                                       threads)
         log(f"[bench] batched: {extra['batched']}")
         log("[bench] K-means (member centres) on the packed matrix")
         extra["kmedoids"] = kmedoids_leg(cl, torch, main_out, N, max(3, args.steps // 3))
@@ -478,7 +598,6 @@ def main():
         extra["backward"] = backward_leg(cl, torch, max(3, args.steps // 2))
         log(f"[bench] backward: {extra['backward']}")
 
-    threads = max(1, min(16, os.cpu_count() or 1))
     errs, cpu = (None, None)
     if not (args.no_error and args.no_cpu_baseline):
         log(f"[bench] oracle leg on {threads} host threads")

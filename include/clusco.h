@@ -90,6 +90,15 @@ const char *clusco_last_error(clusco_handle h);
  * for error studies).  Defaults are the tolerances listed above. */
 clusco_status clusco_set_tolerance(clusco_handle h, clusco_precision p, double tol);
 
+/* The error model behind the fix-up (derived from Eq. 2: an error d of the
+ * contraction moves L cRMSD^2 by 2d).  For precision p and models of L atoms,
+ * *eps is the relative contraction error the library assumes: the score s of
+ * a pair with radii E_i = L R_i^2, E_j is trusted when
+ * eps (E_i + E_j) / (L s) <= tol / 2 and recomputed in FP64 otherwise.  eps
+ * grows with the FP32 accumulation steps (sqrt of the padded length) and, for
+ * SPLIT_BF16, includes the dropped lo*lo' products; it is 0 for FP64. */
+clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L, double *eps);
+
 /* ----------------------------------------------------------- all-vs-all */
 
 /* Workspace bytes for clusco_crmsd_matrix with these sizes (0 if invalid). */
@@ -145,13 +154,20 @@ clusco_status clusco_stage_times(clusco_handle h, double ms[3], int *calls);
 size_t clusco_crmsd_batched_workspace_size(clusco_handle h, int32_t E, const int64_t *h_N,
                                            const int64_t *h_L, clusco_precision p);
 
-/* E independent ensembles in one launch sequence.  Ensemble e has h_N[e]
+/* E independent ensembles in one launch sequence: Eq. 2 over several decoy
+ * sets of uneven size (Results and Discussion: the I-TASSER benchmark of 56
+ * targets, each clustered on its own; Table 1).  Ensemble e has h_N[e]
  * models of h_L[e] atoms starting at float element h_coord_off[e] of coords,
  * and its packed output (h_N[e](h_N[e]-1)/2 scores) starts at float element
  * h_out_off[e] of out.  h_* are HOST arrays read during the call; the plan
  * built from them is cached in the handle, so repeated calls with the same
- * shapes enqueue without host-side planning.  Ensembles may not overlap in
- * out. */
+ * shapes enqueue without host-side planning; outside a graph capture the
+ * plan's launches are themselves replayed from a cached hipGraph.  Under the
+ * caller's own stream capture the call allocates nothing: it needs a plan
+ * cached by an earlier call with the same shapes (else
+ * CLUSCO_ERR_UNSUPPORTED), and such a plan stays alive until clusco_destroy
+ * because the caller's graph holds its device table.  Ensembles may not
+ * overlap in out. */
 clusco_status clusco_crmsd_batched(clusco_handle h, int32_t E, const int64_t *h_N,
                                    const int64_t *h_L, const int64_t *h_coord_off,
                                    const int64_t *h_out_off, const float *coords,

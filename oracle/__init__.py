@@ -11,7 +11,7 @@ as a direct sum over atom pairs.  Every function takes float32 or float64
 coordinates and promotes them exactly to float64.  ``cmo*`` give the contact map overlap (Algorithms, Eq. 6-7)
 with integer contact counts.  ``kmedoids`` clusters a
 packed float32 score matrix (K-means with member centres, the representative
-by the smallest <R>/f) with exact integer sums.
+by the smallest <R>/f) with plain FP64 sums of the scores.
 
 Parity status: pinned (see ``tests/test_oracle_*.py``: invariants, closed
 forms, library-routine equalities, brute force on tiny inputs, finite
@@ -74,9 +74,11 @@ def _load():
     lib.oracle_cmo_pairs.argtypes = [dp, i64, i64, ctypes.c_double, lp, lp, i64, dp, cint]
     lib.oracle_cmo_matrix.restype = cint
     lib.oracle_cmo_pairs.restype = cint
+    lib.oracle_cmo_near_ties.argtypes = [dp, i64, i64, ctypes.c_double, ctypes.c_double, lp]
+    lib.oracle_cmo_near_ties.restype = cint
     i32p = ctypes.POINTER(ctypes.c_int32)
     fp = ctypes.POINTER(ctypes.c_float)
-    lib.oracle_kmedoids.argtypes = [fp, i64, i64, i32p, i64, i32p, i32p, lp, dp, lp]
+    lib.oracle_kmedoids.argtypes = [fp, i64, i64, i32p, i64, i32p, i32p, lp, dp, lp, dp]
     lib.oracle_kmedoids.restype = cint
     for f in ("oracle_crmsd_matrix", "oracle_crmsd_pairs", "oracle_crmsd_cross",
               "oracle_crmsd_grad_pair", "oracle_crmsd_matrix_grad", "oracle_crmsd_cross_grad",
@@ -251,8 +253,10 @@ def cmo_pairs(x, I, J, cutoff: float, threads: int = 0) -> np.ndarray:
 
 def kmedoids(D, N: int, k: int, init, max_iter: int = 100) -> dict:
     """K-means over a packed float32 score matrix with members as centres
-    (K-medoids, alternating assignment / update), exact int64 sums of the
-    scores rounded to 2^-20, and the representative cluster by min <R>/f.
+    (K-medoids, alternating assignment / update), plain FP64 sums of the
+    scores, and the representative cluster by min <R>/f.  ``tie_margin`` is
+    the smallest (second smallest - smallest in-cluster sum) / (n - 1) met by
+    any update: how close the trajectory came to a tie, per summed score.
     See the clustering section of crmsd_oracle.c for the exact rules."""
     D = np.ascontiguousarray(D, dtype=np.float32)
     assert D.shape == (N * (N - 1) // 2,)
@@ -262,17 +266,32 @@ def kmedoids(D, N: int, k: int, init, max_iter: int = 100) -> dict:
     size = np.zeros(k, np.int64)
     mean_r = np.zeros(k)
     info = np.zeros(3, np.int64)
+    margin = np.zeros(1)
     i32p = ctypes.POINTER(ctypes.c_int32)
     lp = ctypes.POINTER(ctypes.c_int64)
     rc = _load().oracle_kmedoids(D.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), N, k,
                                  init.ctypes.data_as(i32p), max_iter, label.ctypes.data_as(i32p),
                                  med.ctypes.data_as(i32p), size.ctypes.data_as(lp), _p(mean_r),
-                                 info.ctypes.data_as(lp))
+                                 info.ctypes.data_as(lp), _p(margin))
     _check(rc, "kmedoids")
     rep = int(info[0])
     return {"labels": label, "medoids": med, "sizes": size, "mean_r": mean_r,
             "rep_cluster": rep, "representative": int(med[rep]) if rep >= 0 else -1,
-            "iterations": int(info[1]), "converged": bool(info[2])}
+            "iterations": int(info[1]), "converged": bool(info[2]),
+            "tie_margin": float(margin[0])}
+
+
+def cmo_near_ties(x, cutoff: float, rel: float = 1e-12) -> np.ndarray:
+    """Per model of an [N,L,3] ensemble, the number of atom pairs whose
+    squared distance is within rel * cutoff^2 of cutoff^2 (where another
+    rounding of the same squared distance could decide the contact the
+    other way).  A comparison diagnostic, not part of the method."""
+    x = _d(x)
+    cnt = np.zeros(x.shape[0], np.int64)
+    _check(_load().oracle_cmo_near_ties(_p(x), x.shape[0], x.shape[1], float(cutoff), float(rel),
+                                        cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+           "cmo_near_ties")
+    return cnt
 
 
 def packed_index(i, j, N):

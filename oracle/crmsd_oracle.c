@@ -476,23 +476,23 @@ int oracle_drmsd_pairs(const double *X, int64_t N, int64_t L, const int64_t *I, 
  *   update  each cluster's new medoid is the member with the smallest sum of
  *           scores to the other members (ties to the lowest model index);
  * repeated until no medoid changes or max_iter updates have run (then one
- * more assignment).  Sums are exact: each score is rounded once to a
- * multiple of 2^-20 (q = rint(d 2^20), an integer) and summed in int64, so
- * the decisions do not depend on summation order.  Scores must be finite,
- * non-negative and below 2^22.
+ * more assignment).  The sums are plain FP64 sums of the float32 scores in
+ * increasing model order.
  * Representative: n_c members, f = n_c / N, <R> = the mean score over the
- * n_c (n_c - 1) / 2 pairs of cluster c (from the same exact sums); the
- * representative cluster minimises <R> / f (clusters of one model are not
- * eligible; ties to the lowest index) and its medoid is the representative
- * model. */
+ * n_c (n_c - 1) / 2 pairs of cluster c; the representative cluster minimises
+ * <R> / f (clusters of one model are not eligible; ties to the lowest index)
+ * and its medoid is the representative model.
+ *
+ * Diagnostic (not part of the method): tie_margin receives the smallest, over
+ * every update and every cluster of n > 1 members, of (second smallest sum -
+ * smallest sum) / (n - 1), i.e. how close any update came to a tie, per
+ * summed score (+infinity when no update compared two members). */
 static double packed_at(const float *D, int64_t N, int64_t i, int64_t j)
 {
     if (i == j) return 0.0;
     if (i > j) { int64_t t = i; i = j; j = t; }
     return (double)D[i * (2 * N - i - 1) / 2 + (j - i - 1)];
 }
-
-static int64_t quant(double d) { return (int64_t)nearbyint(d * 1048576.0); }
 
 static void km_assign(const float *D, int64_t N, int64_t k, const int32_t *med, int32_t *label)
 {
@@ -511,20 +511,20 @@ static void km_assign(const float *D, int64_t N, int64_t k, const int32_t *med, 
     }
 }
 
-/* cost[i] = sum over the other members j of i's cluster of q(D(i, j)). */
-static void km_costs(const float *D, int64_t N, const int32_t *label, int64_t *cost)
+/* cost[i] = sum over the other members j of i's cluster of D(i, j). */
+static void km_costs(const float *D, int64_t N, const int32_t *label, double *cost)
 {
     for (int64_t i = 0; i < N; ++i) {
-        int64_t s = 0;
+        double s = 0.0;
         for (int64_t j = 0; j < N; ++j)
-            if (j != i && label[j] == label[i]) s += quant(packed_at(D, N, i, j));
+            if (j != i && label[j] == label[i]) s += packed_at(D, N, i, j);
         cost[i] = s;
     }
 }
 
 int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, int64_t max_iter,
                     int32_t *label, int32_t *medoid, int64_t *size, double *mean_r,
-                    int64_t *info)
+                    int64_t *info, double *tie_margin)
 {
     if (N < 1 || k < 1 || k > N || max_iter < 0) return 1;
     for (int64_t c = 0; c < k; ++c) {
@@ -533,8 +533,9 @@ int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, i
             if (init[e] == init[c]) return 3;
         medoid[c] = init[c];
     }
-    int64_t *cost = malloc(sizeof(int64_t) * N);
+    double *cost = malloc(sizeof(double) * N);
     if (!cost) return 4;
+    double margin = INFINITY;
     int64_t it = 0, converged = 0;
     while (it < max_iter) {
         km_assign(D, N, k, medoid, label);
@@ -542,9 +543,19 @@ int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, i
         ++it;
         int changed = 0;
         for (int64_t c = 0; c < k; ++c) {
-            int64_t best = -1;
+            int64_t best = -1, n = 0;
             for (int64_t i = 0; i < N; ++i)
-                if (label[i] == c && (best < 0 || cost[i] < cost[best])) best = i;
+                if (label[i] == c) {
+                    ++n;
+                    if (best < 0 || cost[i] < cost[best]) best = i;
+                }
+            if (n > 1) {
+                double second = INFINITY;
+                for (int64_t i = 0; i < N; ++i)
+                    if (label[i] == c && i != best && cost[i] < second) second = cost[i];
+                const double gap = (second - cost[best]) / (double)(n - 1);
+                if (gap < margin) margin = gap;
+            }
             if (best != medoid[c]) { medoid[c] = (int32_t)best; changed = 1; }
         }
         if (!changed) { converged = 1; break; }
@@ -556,11 +567,12 @@ int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, i
     int64_t rep = -1;
     double rep_score = 0.0;
     for (int64_t c = 0; c < k; ++c) {
-        int64_t n = 0, s = 0;
+        int64_t n = 0;
+        double s = 0.0;
         for (int64_t i = 0; i < N; ++i)
             if (label[i] == c) { ++n; s += cost[i]; }
         size[c] = n;
-        mean_r[c] = n > 1 ? ((double)s / 1048576.0) / ((double)n * (double)(n - 1)) : 0.0;
+        mean_r[c] = n > 1 ? s / ((double)n * (double)(n - 1)) : 0.0;
         if (n > 1) {
             double score = mean_r[c] * ((double)N / (double)n);
             if (rep < 0 || score < rep_score) { rep = c; rep_score = score; }
@@ -569,6 +581,7 @@ int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, i
     info[0] = rep;
     info[1] = it;
     info[2] = converged;
+    if (tie_margin) *tie_margin = margin;
     free(cost);
     return 0;
 }
@@ -578,15 +591,17 @@ int oracle_kmedoids(const float *D, int64_t N, int64_t k, const int32_t *init, i
  * contact when their distance is below the cut-off, C_pq = [|x_p - x_q| <
  * cutoff]; the score of two models is the Sorensen index of their contact
  * sets, S = 100 * 2 n(A and B) / (n(A) + n(B)), with n the number of
- * contacts.  Each contact is decided on d^2 = fma(u, u, fma(v, v, w w)) <
- * cutoff^2 in FP64 (u, v, w the exact FP64 coordinate differences); the
- * counts are integers.  S = 0 when neither model has a contact. */
+ * contacts.  Each contact is decided on the squared distance
+ * u*u + v*v + w*w < cutoff^2 in FP64 (u, v, w the exact FP64 coordinate
+ * differences; the library is built without floating-point contraction, so
+ * every product and sum is rounded on its own); the counts are integers.
+ * S = 0 when neither model has a contact. */
 static int in_contact(const double *X, int64_t p, int64_t q, double c2)
 {
     const double u = X[3 * p] - X[3 * q];
     const double v = X[3 * p + 1] - X[3 * q + 1];
     const double w = X[3 * p + 2] - X[3 * q + 2];
-    return fma(u, u, fma(v, v, w * w)) < c2;
+    return u * u + v * v + w * w < c2;
 }
 
 double oracle_cmo_pair(const double *A, const double *B, int64_t L, double cutoff)
@@ -628,5 +643,30 @@ int oracle_cmo_pairs(const double *X, int64_t N, int64_t L, double cutoff, const
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < P; ++p)
         out[p] = oracle_cmo_pair(X + 3 * L * I[p], X + 3 * L * J[p], L, cutoff);
+    return 0;
+}
+
+/* Diagnostic for comparisons (not part of the method): per model, the number
+ * of atom pairs whose squared distance lies within rel * cutoff^2 of
+ * cutoff^2, where a differently rounded evaluation of the same squared
+ * distance could take the other side of the strict cut-off. */
+int oracle_cmo_near_ties(const double *X, int64_t N, int64_t L, double cutoff, double rel,
+                         int64_t *count)
+{
+    if (N < 0 || L < 1 || !(cutoff >= 0.0) || !(rel >= 0.0)) return 1;
+    const double c2 = cutoff * cutoff, band = rel * c2;
+    for (int64_t m = 0; m < N; ++m) {
+        const double *x = X + 3 * L * m;
+        int64_t n = 0;
+        for (int64_t p = 0; p < L; ++p)
+            for (int64_t q = p + 1; q < L; ++q) {
+                const double u = x[3 * p] - x[3 * q];
+                const double v = x[3 * p + 1] - x[3 * q + 1];
+                const double w = x[3 * p + 2] - x[3 * q + 2];
+                const double d2 = u * u + v * v + w * w;
+                n += fabs(d2 - c2) <= band;
+            }
+        count[m] = n;
+    }
     return 0;
 }

@@ -55,6 +55,7 @@ def lib():
             "clusco_status_string": (ctypes.c_char_p, [st]),
             "clusco_last_error": (ctypes.c_char_p, [vp]),
             "clusco_set_tolerance": (st, [vp, st, d]),
+            "clusco_flag_epsilon": (st, [vp, st, i64, ctypes.POINTER(d)]),
             "clusco_crmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_drmsd_workspace_size": (sz, [vp, i64, i64, st]),
@@ -141,6 +142,16 @@ def set_tolerance(precision, tol: float, device: int = 0):
     """Fix-up tolerance (A) for a precision; tol <= 0 disables the FP64 fix-up."""
     h = handle(device)
     _check(lib().clusco_set_tolerance(h, _prec(precision), float(tol)), h, "clusco_set_tolerance")
+
+
+def flag_epsilon(precision, L: int, device: int = 0) -> float:
+    """Relative contraction error the fix-up flag assumes for this precision
+    and model length (see clusco_flag_epsilon)."""
+    h = handle(device)
+    e = ctypes.c_double()
+    _check(lib().clusco_flag_epsilon(h, _prec(precision), int(L), ctypes.byref(e)), h,
+           "clusco_flag_epsilon")
+    return float(e.value)
 
 
 def workspace_size(N: int, L: int, precision="fp32", device: int = 0) -> int:

@@ -29,6 +29,9 @@ struct BatchPlan {
     // cached graph for the last buffers it was captured with
     hipGraphExec_t exec = nullptr;
     const void *g_coords = nullptr, *g_out = nullptr, *g_ws = nullptr;
+    // used inside a graph the caller captured: its table address is baked
+    // into that graph, so the plan is kept until the handle is destroyed
+    bool pinned = false;
 };
 
 } // namespace
@@ -36,7 +39,6 @@ struct BatchPlan {
 struct clusco_ctx {
     int device;
     double tol[NMODES];   // fix-up tolerance per precision (A); <= 0 disables
-    double eps[NMODES];   // calibrated relative error of the contraction per precision
     std::string last_error;
     // stage timing (measurement only): 4 events per recorded call
     std::vector<hipEvent_t> events;
@@ -102,12 +104,52 @@ struct DeviceGuard {
     }
 };
 
+// Error model of the contraction, the basis of the FP64 fix-up flag.
+//
+// Eq. 2 gives L s^2 = E_i + E_j - 2 S(H), S the signed sum of the singular
+// values of H.  An error dH of the contraction moves S by at most about
+// |dH| and hence the score s by d(L s^2) / (2 L s).  Writing the error of
+// S as eps (E_i + E_j) / 2 bounds the score error by
+//     err(s) <= eps (E_i + E_j) / (L s),
+// which grows without bound as s -> 0: small scores need the fix-up.  eps
+// has two measured parts:
+//   accumulation  every MFMA step rounds the FP32 accumulators once, so an
+//                 accumulator that grows steadily to about E carries about
+//                 2^-24 E sqrt(steps / 3) of rounding (a random walk over
+//                 the steps): steps = Lp/2 (FP32, 2 atoms per step),
+//                 3 Lp/16 (split, 16 atoms per product, three products) or
+//                 4 Lp/16 (split x4);
+//   dropped term  split-BF16 x3 leaves out lo*lo' (|lo| <= 2^-9 |a|): per
+//                 atom a product of about 2^-18 |a||b| with a random sign,
+//                 2^-18 E / sqrt(L) summed (split-FP16 x3 drops 2^-24 |a||b|,
+//                 which the accumulation part covers; x4 drops nothing).
+// The epilogue's unrefined hardware reciprocal square roots (relative error
+// below 6e-8) add R_RSQ.  The coefficients are fitted to GPU measurements of
+// max err s L / (E_i + E_j) with the fix-up off (FP64 oracle, L = 150, 300
+// and 500); EPS_MARGIN keeps every measured maximum at most 1 / EPS_MARGIN
+// of the model's value.
+constexpr double K_ACC = 0.70, K_DROP = 1.90, R_RSQ = 6e-8, EPS_MARGIN = 1.5;
+
+double contraction_eps(int mode, int64_t L)
+{
+    if (mode == MODE_FP64) return 0.0;
+    const double Lp = (double)round_up(L, kblock(mode));
+    const double steps = mode == MODE_FP32     ? Lp / 2.0
+                         : mode == MODE_BF16X4 ? Lp / 4.0
+                                               : 3.0 * Lp / 16.0;
+    const double acc = std::ldexp(1.0, -24) * std::sqrt(steps / 3.0);
+    const double drop = mode == MODE_BF16 ? std::ldexp(1.0, -18) / std::sqrt((double)L) : 0.0;
+    return EPS_MARGIN * (K_ACC * acc + K_DROP * drop + R_RSQ);
+}
+
+// Flag a pair when its score bound eps (E_i + E_j) / (L s) exceeds half the
+// tolerance, i.e. when s < flag_coef (E_i + E_j).  An unflagged pair's error
+// is then at most tol / (2 EPS_MARGIN) by the measured maxima.
 double flag_coef(clusco_handle h, int mode, int64_t L)
 {
     const double tol = h->tol[mode];
     if (mode == MODE_FP64 || !(tol > 0.0)) return -1.0;
-    // flag when  eps (E_i + E_j) / (L score) > tol / 2
-    return 2.0 * h->eps[mode] / ((double)L * tol);
+    return 2.0 * contraction_eps(mode, L) / ((double)L * tol);
 }
 
 void stage_mark(clusco_handle h, int k, hipStream_t s)
@@ -377,12 +419,10 @@ std::vector<int64_t> batch_key(clusco_handle h, int mode, const BatchInput &b, b
     k.reserve(4 * b.E + 4);
     k.push_back(mode);
     k.push_back(b.E);
-    double tol = h->tol[mode], eps = h->eps[mode];
-    int64_t t, ep;
+    double tol = h->tol[mode];
+    int64_t t;
     memcpy(&t, &tol, 8);
-    memcpy(&ep, &eps, 8);
     k.push_back(t);
-    k.push_back(ep);
     for (int32_t e = 0; e < b.E; ++e) {
         k.push_back(b.N[e]);
         k.push_back(b.L[e]);
@@ -443,18 +483,25 @@ void free_plan(BatchPlan &p)
     p.dtab = nullptr;
 }
 
-clusco_status get_plan(clusco_handle h, int mode, const BatchInput &b, BatchPlan **out)
+BatchPlan *find_plan(clusco_handle h, const std::vector<int64_t> &key)
 {
-    std::vector<int64_t> key = batch_key(h, mode, b, true);
     for (auto it = h->plans.begin(); it != h->plans.end(); ++it) {
         if (it->key == key) {
             h->plans.splice(h->plans.begin(), h->plans, it);
-            *out = &h->plans.front();
-            return CLUSCO_OK;
+            return &h->plans.front();
         }
     }
+    return nullptr;
+}
+
+// Builds and uploads a new plan (one hipMalloc and a blocking copy: never
+// called while the caller's stream is being captured).  The least recently
+// used unpinned plans beyond MAX_PLANS are freed.
+clusco_status create_plan(clusco_handle h, int mode, const BatchInput &b,
+                          std::vector<int64_t> key, BatchPlan **out)
+{
     BatchPlan p;
-    p.key = key;
+    p.key = std::move(key);
     std::vector<ModelSet> sets;
     std::vector<Problem> probs;
     p.ws_total = plan_layout(h, mode, b, &sets, &probs, &p.off_list, &p.T, &p.n_wtiles,
@@ -476,9 +523,14 @@ clusco_status get_plan(clusco_handle h, int mode, const BatchInput &b, BatchPlan
         }
     }
     h->plans.push_front(std::move(p));
-    while (h->plans.size() > MAX_PLANS) {
-        free_plan(h->plans.back());
-        h->plans.pop_back();
+    size_t unpinned = 0;
+    for (auto it = h->plans.begin(); it != h->plans.end();) {
+        if (!it->pinned && ++unpinned > MAX_PLANS) {
+            free_plan(*it);
+            it = h->plans.erase(it);
+        } else {
+            ++it;
+        }
     }
     *out = &h->plans.front();
     return CLUSCO_OK;
@@ -526,17 +578,6 @@ clusco_status clusco_create(clusco_handle *h, int device)
     c->tol[MODE_BF16X4] = 5e-4;
     c->tol[MODE_FP16] = 1e-4;
     c->tol[MODE_FP64] = 1e-6;
-    // effective relative error of the contraction (err * score * L / (E_i +
-    // E_j)) measured on the GPU: the largest over 2e5 pairs at L = 150 (the
-    // fix-up flag's factor-four margin covers the up to 1.8x larger maxima
-    // seen at L = 300 and the < 6e-8 of the unrefined reciprocal square
-    // roots in the tile epilogue).  A larger epsilon grows the fix-up fast:
-    // 8e-7 instead of 7e-7 for split-bf16 flags 11x more blocks at N = 20,000.
-    c->eps[MODE_FP32] = 3e-7;
-    c->eps[MODE_BF16] = 7e-7;
-    c->eps[MODE_BF16X4] = 3e-7;
-    c->eps[MODE_FP16] = 1.6e-7;
-    c->eps[MODE_FP64] = 0.0;
     *h = c;
     return CLUSCO_OK;
 }
@@ -560,6 +601,15 @@ clusco_status clusco_set_tolerance(clusco_handle h, clusco_precision p, double t
     if (!h) return CLUSCO_ERR_INVALID_ARG;
     if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
     h->tol[mode_of(p)] = tol;
+    return CLUSCO_OK;
+}
+
+clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L, double *eps)
+{
+    if (!h || !eps) return CLUSCO_ERR_INVALID_ARG;
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need L >= 1");
+    *eps = contraction_eps(mode_of(p), L);
     return CLUSCO_OK;
 }
 
@@ -683,18 +733,33 @@ clusco_status clusco_crmsd_batched(clusco_handle h, int32_t E, const int64_t *h_
 
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
-    BatchPlan *plan = nullptr;
-    st = get_plan(h, mode, b, &plan);
-    if (st != CLUSCO_OK) return st;
     hipStream_t s = (hipStream_t)stream;
 
-    // Direct launches while stage timing records or while the caller is
-    // itself capturing a graph; otherwise replay (or capture) the plan's graph.
+    // Inside the caller's own graph capture nothing may allocate or copy
+    // synchronously: the plan must already exist (an earlier call with the
+    // same shapes), and it is pinned because the caller's graph keeps its
+    // table address.  Otherwise launches are direct while stage timing
+    // records, else the plan's own graph is replayed (captured first).
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(s, &cs);
     if (e != hipSuccess) return hip_fail(h, e, "query stream capture");
+    std::vector<int64_t> key = batch_key(h, mode, b, true);
+    BatchPlan *plan = find_plan(h, key);
+    if (cs != hipStreamCaptureStatusNone) {
+        if (!plan)
+            return fail(h, CLUSCO_ERR_UNSUPPORTED,
+                        "no cached plan for these shapes under graph capture: make one call "
+                        "with the same shapes outside the capture first");
+        plan->pinned = true;
+        return enqueue(h, mode, coords, coords, (char *)ws, out, nullptr, plan, TK_BATCH, s,
+                       false);
+    }
+    if (!plan) {
+        st = create_plan(h, mode, b, std::move(key), &plan);
+        if (st != CLUSCO_OK) return st;
+    }
     const bool timing = h->used < h->slots;
-    if (timing || cs != hipStreamCaptureStatusNone)
+    if (timing)
         return enqueue(h, mode, coords, coords, (char *)ws, out, nullptr, plan, TK_BATCH, s,
                        timing);
 

@@ -243,3 +243,22 @@ def test_only_declared_functions_are_exported(L):
     c_names = {ln.split()[-1] for ln in out.splitlines()
                if ln.split()[1] == "T" and not ln.split()[-1].startswith("_")}
     assert c_names == set(declared_functions())
+
+
+def test_flag_epsilon_model(L, h):
+    """The error model's shape: none in FP64, the accumulation part growing
+    with sqrt(steps), the x3 split above x4 (its dropped lo*lo' term)."""
+    def eps(p, n):
+        e = ctypes.c_double(-1.0)
+        assert L.clusco_flag_epsilon(h, p, n, ctypes.byref(e)) == binding.OK
+        return e.value
+    assert eps(3, 150) == 0.0
+    for p in (0, 1, 2, 4):
+        assert 0.0 < eps(p, 150) < 1e-5
+    assert eps(1, 150) > eps(4, 150) > 0.0
+    assert eps(0, 600) > eps(0, 150) > eps(0, 16)
+    assert eps(4, 640) > eps(4, 160)
+    e = ctypes.c_double()
+    assert L.clusco_flag_epsilon(h, 9, 150, ctypes.byref(e)) == binding.ERR_UNSUPPORTED
+    assert L.clusco_flag_epsilon(h, 0, 0, ctypes.byref(e)) == binding.ERR_INVALID_ARG
+    assert L.clusco_flag_epsilon(h, 0, 150, None) == binding.ERR_INVALID_ARG

@@ -1,7 +1,14 @@
 """GPU parity of the all-vs-all contact map overlap (Algorithms, Eq. 6-7)
 against the oracle: contact counts are exact integers on both sides and the
 score is one correctly rounded FP64 quotient, so the float32 output must equal
-the oracle's value rounded to float32, element by element."""
+the oracle's value rounded to float32, element by element.
+
+The oracle decides each contact on u*u + v*v + w*w < cutoff^2 with every
+operation rounded on its own; the kernel evaluates the same FP64 squared
+distance with fused multiply-adds.  The two can only disagree on an atom pair
+whose squared distance lies within a few FP64 ulps of cutoff^2; a score may
+differ from the oracle's only for a model pair where the oracle reports such
+a near tie (none occur in these inputs; any would be printed)."""
 import numpy as np
 import pytest
 
@@ -24,6 +31,20 @@ def say(*a):
     print(*a, flush=True)
 
 
+def assert_matches(x, cutoff, got, want, I=None, J=None):
+    """Element-wise equality, except on pairs with an oracle-reported near tie."""
+    bad = got != want
+    if not bad.any():
+        return
+    N = x.shape[0]
+    if I is None:
+        I, J = np.triu_indices(N, 1)
+    ties = oracle.cmo_near_ties(x, cutoff, 1e-14)
+    ok = (ties[I] > 0) | (ties[J] > 0)
+    say(f"  {int(bad.sum())} scores differ; near-tie pairs among them: {int(ok[bad].sum())}")
+    assert ok[bad].all(), np.abs(got - want)[bad & ~ok].max()
+
+
 def run(cl, x, cutoff):
     xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
     out = cl.cmo_matrix(xd, cutoff)
@@ -36,8 +57,7 @@ def test_n300_l60_all_pairs_exact(cl, cutoff):
     say(f"[cmo] N=300 L=60 all pairs, cutoff {cutoff}")
     x = synth.make_ensemble(21, 300, 60, sigma=(0.3, 5.0)).astype(np.float32)
     want = oracle.cmo_matrix(x, cutoff).astype(np.float32)
-    got = run(cl, x, cutoff)
-    assert np.array_equal(got, want), np.abs(got - want).max()
+    assert_matches(x, cutoff, run(cl, x, cutoff), want)
 
 
 @pytest.mark.parametrize("N,L", [(2, 2), (3, 3), (5, 7), (33, 17), (65, 33), (129, 64),
@@ -46,7 +66,7 @@ def test_ragged_shapes_exact(cl, N, L):
     say(f"[cmo] ragged N={N} L={L}")
     x = synth.make_ensemble(3000 + N + L, N, L, sigma=(0.3, 5.0)).astype(np.float32)
     want = oracle.cmo_matrix(x, 8.0).astype(np.float32)
-    assert np.array_equal(run(cl, x, 8.0), want)
+    assert_matches(x, 8.0, run(cl, x, 8.0), want)
 
 
 def test_edge_cases(cl):
@@ -85,5 +105,5 @@ def test_n20000_l150_sampled_exact(cl):
     J = np.r_[J, jj, np.arange(1, 200), np.full(199, 19999)]
     got = out[torch.from_numpy(oracle.packed_index(I, J, 20000)).cuda()].cpu().numpy()
     want = oracle.cmo_pairs(x, I, J, 8.0).astype(np.float32)
-    assert np.array_equal(got, want)
+    assert_matches(x, 8.0, got, want, I, J)
     assert float(out.min()) >= 0.0 and float(out.max()) <= 100.0

@@ -1,19 +1,29 @@
 """GPU parity of the clustering of the score matrix (K-means with member
 centres and the min <R>/f representative) against the oracle, on the very
-same float32 matrix: labels, medoids, sizes, iteration count and the
-representative must match exactly (all decisions are exact: float32
-comparisons and integer sums), and <R> bit for bit (the same FP64 formula
-applied to the same integers).  At N=20000 the fixed-point properties are
-checked instead."""
+same float32 matrix.
+
+The oracle sums the float32 scores in FP64, as the definition states.  The
+kernel sums each score rounded to a multiple of 2^-20 in int64 (an
+order-independent sum), so a member's sum differs from the oracle's by at
+most (n - 1) 2^-21 and two members' sums can swap order only when the
+oracle's gap between them is at most (n - 1) 2^-20.  Hence:
+  * when every update of the oracle's run cleared that bound (its
+    tie_margin > 2^-20), labels, medoids, sizes, the iteration count and the
+    representative must be identical, and <R> within 2^-21;
+  * otherwise the GPU's final state must still be a valid fixed point by
+    the oracle's FP64 arithmetic: every label the nearest medoid (exact
+    float32 comparison, lowest cluster on ties), every medoid an in-cluster
+    minimiser of the FP64 sum to within (n - 1) 2^-20, <R> within 2^-21 of
+    the FP64 mean, and the representative minimal to within its bound."""
 import numpy as np
 import pytest
 
 import oracle
+from kmedoids_check import Q, check_fixed_point
 from paper_1302_4000_amd import synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
 
 @pytest.fixture(scope="module")
 def cl():
@@ -37,13 +47,18 @@ def compare(cl, D_np, N, k, init, max_iter=100):
     for n, t in other.items():
         assert np.array_equal(t.cpu().numpy(), got[n]), n
     want = oracle.kmedoids(D_np, N, k, init, max_iter)
-    assert np.array_equal(got["labels"], want["labels"])
-    assert np.array_equal(got["medoids"], want["medoids"])
-    assert np.array_equal(got["sizes"], want["sizes"])
-    assert np.array_equal(got["mean_r"], want["mean_r"])
-    assert got["info"][0] == want["rep_cluster"]
-    assert got["info"][1] == want["iterations"]
-    assert bool(got["info"][2]) == want["converged"]
+    if want["tie_margin"] > Q * (1 + 1e-6) + 1e-12:
+        assert np.array_equal(got["labels"], want["labels"])
+        assert np.array_equal(got["medoids"], want["medoids"])
+        assert np.array_equal(got["sizes"], want["sizes"])
+        assert np.abs(got["mean_r"] - want["mean_r"]).max() <= Q / 2 + 1e-9
+        assert got["info"][0] == want["rep_cluster"]
+        assert got["info"][1] == want["iterations"]
+        assert bool(got["info"][2]) == want["converged"]
+    else:
+        say(f"  oracle tie margin {want['tie_margin']:.3g} within the kernel's 2^-20 "
+            f"quantum: checking the fixed point instead of the trajectory")
+    check_fixed_point(np.ascontiguousarray(D_np, dtype=np.float32), N, k, got)
     return want
 
 
@@ -88,29 +103,7 @@ def test_n20000_fixed_point(cl):
     Dd = cl.crmsd_matrix(torch.from_numpy(x).cuda(), "bf16")
     init = [(c * N) // k for c in range(k)]
     got = {n: t.cpu().numpy() for n, t in cl.kmedoids(Dd, N, k, init, 200).items()}
-    lab, med = got["labels"], got["medoids"]
     assert got["info"][2] == 1 and 1 <= got["info"][1] <= 200
-    assert len(set(med.tolist())) == k and got["sizes"].sum() == N
-    D = Dd.cpu().numpy()
-
-    def score(i, j):
-        i, j = np.minimum(i, j), np.maximum(i, j)
-        return D[oracle.packed_index(i, j, N)].astype(np.float64)
-    idx = np.arange(N)
-    dist = np.stack([np.where(idx == m, 0.0, score(idx, np.full(N, m))) for m in med], 1)
-    want = np.argmin(dist, 1)                       # first minimum = lowest cluster on ties
-    for c, m in enumerate(med):
-        want[m] = c
-    assert np.array_equal(lab, want)
-    for c in range(k):
-        mem = np.flatnonzero(lab == c)
-        cost = np.zeros(len(mem))
-        for s0 in range(0, len(mem), 256):           # in-cluster sums, 256 rows at a time
-            I, J = np.meshgrid(mem[s0:s0 + 256], mem, indexing="ij")
-            q = np.where(I == J, 0.0, np.rint(score(I.ravel(), J.ravel()).reshape(I.shape) * 2.0**20))
-            cost[s0:s0 + 256] = q.sum(1)
-        assert med[c] == mem[int(np.argmin(cost))]
-        n = len(mem)
-        if n > 1:
-            assert got["mean_r"][c] == (cost.sum() / 2.0**20) / (n * (n - 1.0))
+    assert got["sizes"].sum() == N
+    check_fixed_point(Dd.cpu().numpy(), N, k, got)
     say(f"  iterations {got['info'][1]}, representative cluster {got['info'][0]}")

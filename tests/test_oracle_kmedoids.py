@@ -3,7 +3,9 @@ centres, representative by the smallest <R>/f), checked against facts that do
 not come from the oracle: 1-D groups where the medoid is the median and the
 mean pairwise distance has a closed form, the lowest-index tie rules, the
 fixed-point property of the result re-derived by brute force on the square
-matrix, k = 1 (the global 1-median) and k = N."""
+matrix (FP64 sums of the float32 scores, as the definition states), k = 1
+(the global 1-median) and k = N, and the tie-margin diagnostic on exact and
+clear-cut cases."""
 import numpy as np
 import pytest
 
@@ -45,6 +47,10 @@ def test_separated_groups_medians_and_closed_forms(orc):
         assert abs(r["mean_r"][c] - s * (n + 1) / 3.0) < 1e-5
     score = [s * (n + 1) / 3.0 * N / n for n, s, _ in groups]
     assert r["rep_cluster"] == int(np.argmin(score)) == 3   # not the tightest group (2): f counts
+    # the closest call of any update: in the final groups the median beats
+    # its neighbours by s per other member, s / (n - 1) after the division;
+    # earlier updates can only have been further from a tie or equal
+    assert 0.0 < r["tie_margin"] <= min(s / (n - 1) for n, s, _ in groups) + 1e-6
     assert r["representative"] == r["medoids"][r["rep_cluster"]]
 
 
@@ -52,6 +58,7 @@ def test_tie_rules(orc):
     # 0,1,2,3: members 1 and 2 tie on the in-cluster sum -> lowest index wins
     r = orc.kmedoids(line_matrix([0, 1, 2, 3, 50]), 5, 2, [3, 4])
     assert list(r["medoids"]) == [1, 4]
+    assert r["tie_margin"] == 0.0                       # the exact tie is reported
     # model 2 is equidistant from medoids 0 and 4 -> the lower cluster index
     r = orc.kmedoids(line_matrix([0, 5, 10, 100, 15]), 5, 2, [1, 4], max_iter=0)
     assert r["labels"][2] == 0 and r["iterations"] == 0
@@ -70,7 +77,7 @@ def test_fixed_point_by_brute_force(orc):
         assert r["converged"]
         med, lab = r["medoids"], r["labels"]
         assert len(set(med)) == k
-        q = np.rint(S.astype(np.float32).astype(np.float64) * 2.0**20)
+        q = S.astype(np.float32).astype(np.float64)
         for m in range(N):                               # nearest medoid, lowest index on ties
             d = S[m, med]
             want = int(np.flatnonzero(med == m)[0]) if m in med else int(np.argmin(d))

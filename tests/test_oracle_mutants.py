@@ -147,6 +147,8 @@ KM_MUTANTS = {
     "no_fraction": ("double score = mean_r[c] * ((double)N / (double)n);",
                     "double score = mean_r[c];"),
     "cost_all_models": ("if (j != i && label[j] == label[i]) s +=", "if (j != i) s +="),
+    "cost_later_members_only": ("        double s = 0.0;\n        for (int64_t j = 0; j < N; ++j)",
+                                "        double s = 0.0;\n        for (int64_t j = i + 1; j < N; ++j)"),
 }
 
 
@@ -189,8 +191,9 @@ def test_kmedoids_mutant_is_caught(tmp_path, name):
 
 
 CMO_MUTANTS = {
-    "non_strict_cutoff": ("return fma(u, u, fma(v, v, w * w)) < c2;",
-                          "return fma(u, u, fma(v, v, w * w)) <= c2;"),
+    "non_strict_cutoff": ("return u * u + v * v + w * w < c2;",
+                          "return u * u + v * v + w * w <= c2;"),
+    "dropped_coordinate": ("return u * u + v * v + w * w < c2;", "return u * u + v * v < c2;"),
     "no_factor_two": ("return (200.0 * (double)nab) / (double)(na + nb);",
                       "return (100.0 * (double)nab) / (double)(na + nb);"),
     "includes_diagonal": ("for (int64_t q = p + 1; q < L; ++q) {\n            const int a = in_contact",
