@@ -111,6 +111,26 @@ clusco_status clusco_crmsd_matrix(clusco_handle h, const float *coords, int64_t 
                                   clusco_precision p, float *out, void *ws, size_t ws_bytes,
                                   void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and result as clusco_crmsd_matrix, with the workspace taken
+ * from a built-in device scratch array of CLUSCO_SCRATCH_BYTES instead of a
+ * caller buffer.  The caller still passes coords and out.  Each device the
+ * library runs on holds its own copy of the scratch from the first
+ * clusco_create on that device until the process ends.  Sizes whose
+ * workspace (clusco_crmsd_workspace_size) exceeds CLUSCO_SCRATCH_BYTES
+ * return CLUSCO_ERR_UNSUPPORTED before anything is enqueued (64 MiB holds
+ * N = 20,000 at L = 150 in every precision).  The call allocates nothing and
+ * never synchronises.  All calls on one device share that device's scratch
+ * and it keeps the last call's contents: calls that overlap on one device
+ * (different streams, or different handles on concurrent streams) race and
+ * must be ordered by the caller.  The prep kernel of every call clears the
+ * counters the later kernels rely on, so no clearing is needed between
+ * calls. */
+#define CLUSCO_SCRATCH_BYTES (64u << 20)
+clusco_status clusco_crmsd_matrix_noalloc(clusco_handle h, const float *coords, int64_t N,
+                                          int64_t L, clusco_precision p, float *out, void *stream);
+
 /* Pairs within a cRMSD cutoff (Results and Discussion: selecting the pairs of
  * models below a threshold, 3.2 A in the paper's example) without storing the
  * N(N-1)/2 matrix.  Every pair (i, j), i < j, whose score (computed exactly as

@@ -58,6 +58,7 @@ def lib():
             "clusco_flag_epsilon": (st, [vp, st, i64, ctypes.POINTER(d)]),
             "clusco_crmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
+            "clusco_crmsd_matrix_noalloc": (st, [vp, vp, i64, i64, st, vp, vp]),
             "clusco_drmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_cluster_workspace_size": (sz, [vp, i64, i32]),
             "clusco_cmo_workspace_size": (sz, [vp, i64, i64]),
@@ -178,6 +179,28 @@ def crmsd_matrix(x: torch.Tensor, precision="fp32", out: torch.Tensor | None = N
     rc = lib().clusco_crmsd_matrix(h, _ptr(x), N, L, p, _ptr(out), _ptr(ws), ws.numel(),
                                    _stream(dev))
     _check(rc, h, "clusco_crmsd_matrix")
+    return out
+
+
+SCRATCH_BYTES = 64 << 20   # CLUSCO_SCRATCH_BYTES
+
+
+def crmsd_matrix_noalloc(x: torch.Tensor, out: torch.Tensor, precision="fp32") -> torch.Tensor:
+    """clusco_crmsd_matrix_noalloc: the packed all-vs-all cRMSD of x into the
+    caller's `out`, using the library's built-in device scratch (allocates
+    nothing; calls on one device must not overlap)."""
+    x = _coords(x)
+    N, L = x.shape[0], x.shape[1]
+    dev = x.device
+    h = handle(dev.index)
+    P = N * (N - 1) // 2
+    if out.numel() != P or out.dtype != torch.float32 or not out.is_contiguous() or \
+            out.device != dev:
+        raise TypeError("out must be a contiguous float32 tensor of N(N-1)/2 elements on "
+                        "the device of x")
+    rc = lib().clusco_crmsd_matrix_noalloc(h, _ptr(x), N, L, _prec(precision), _ptr(out),
+                                           _stream(dev))
+    _check(rc, h, "clusco_crmsd_matrix_noalloc")
     return out
 
 

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,44 @@ struct clusco_ctx {
     // batched plans, most recent first
     std::list<BatchPlan> plans;
     hipStream_t capture = nullptr;
+    // device address of this device's built-in scratch (no-alloc entry
+    // point), looked up once per device when the handle is created
+    void *scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
 };
+
+// Built-in workspace of clusco_crmsd_matrix_noalloc: every device that loads
+// the library holds one copy until the process ends.  Host code never uses
+// the array's name as an address (on the host it is only a stand-in for the
+// symbol); it uses the device address hipGetSymbolAddress returns, kept per
+// device in scratch_ptr.
+static __device__ __align__(256) char scratch[CLUSCO_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];
+hipError_t scratch_status[MAX_DEVICES];
+bool scratch_done[MAX_DEVICES];
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+hipError_t scratch_setup(int dev, void **ptr)
+{
+    *ptr = nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_done[dev]) {
+        void *p = nullptr;
+        scratch_status[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        scratch_ptr[dev] = scratch_status[dev] == hipSuccess ? p : nullptr;
+        scratch_done[dev] = true;
+    }
+    *ptr = scratch_ptr[dev];
+    return scratch_status[dev];
+}
+
+} // namespace
 
 namespace {
 
@@ -578,6 +616,10 @@ clusco_status clusco_create(clusco_handle *h, int device)
     c->tol[MODE_BF16X4] = 5e-4;
     c->tol[MODE_FP16] = 1e-4;
     c->tol[MODE_FP64] = 1e-6;
+    {
+        DeviceGuard g(device);
+        c->scratch_err = g.err != hipSuccess ? g.err : scratch_setup(device, &c->scratch);
+    }
     *h = c;
     return CLUSCO_OK;
 }
@@ -639,6 +681,35 @@ clusco_status clusco_crmsd_matrix(clusco_handle h, const float *coords, int64_t 
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
     return enqueue(h, mode, coords, coords, (char *)ws, out, &s, nullptr, TK_SYM,
+                   (hipStream_t)stream, true);
+}
+
+clusco_status clusco_crmsd_matrix_noalloc(clusco_handle h, const float *coords, int64_t N,
+                                          int64_t L, clusco_precision p, float *out, void *stream)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (N < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0 and L >= 1");
+    if (N > MAX_N) return fail(h, CLUSCO_ERR_UNSUPPORTED, "N above 2^20");
+    if (N < 2) return CLUSCO_OK;
+    if (!coords || !out) return fail(h, CLUSCO_ERR_INVALID_ARG, "null coords or out");
+    if (!aligned(coords, 4) || !aligned(out, 4))
+        return fail(h, CLUSCO_ERR_INVALID_ARG, "coords and out must be 4-byte aligned");
+    const int mode = mode_of(p);
+    const SingleLayout s = single_layout(h, mode, N, L);
+    if (s.total > (size_t)CLUSCO_SCRATCH_BYTES)
+        return fail(h, CLUSCO_ERR_UNSUPPORTED,
+                    "workspace for these N, L exceeds the built-in scratch (CLUSCO_SCRATCH_BYTES); "
+                    "use clusco_crmsd_matrix with a caller workspace");
+    if (h->scratch_err != hipSuccess || !h->scratch)
+        return hip_fail(h, h->scratch_err != hipSuccess ? h->scratch_err : hipErrorInvalidSymbol,
+                        "built-in scratch address");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(h, g.err, "set device");
+    // the prep kernel zeroes the counters at the head of the scratch; nothing
+    // else in it needs to start at zero
+    return enqueue(h, mode, coords, coords, (char *)h->scratch, out, &s, nullptr, TK_SYM,
                    (hipStream_t)stream, true);
 }
 
