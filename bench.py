@@ -53,17 +53,23 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(prec: str, workload: str):
-    """HBM bytes per tile-kernel launch from a committed counter summary, or
-    None when there is none or the kernel changed since it was taken."""
-    pat = os.path.join(ROOT, "profiles", f"tile_{prec}_{workload}_hbm_traffic.md")
+def profile_value(prec: str, workload: str, kind: str, key: str):
+    """A figure from a committed rocprofv3 summary of the tile kernel
+    (profiles/tile_<prec>_<workload>_<kind>.md), or None when there is none
+    or the kernel sources changed since it was taken."""
+    pat = os.path.join(ROOT, "profiles", f"tile_{prec}_{workload}_{kind}.md")
     for f in glob.glob(pat):
         txt = open(f).read()
         m_h = re.search(r"source-sha256:\s*([0-9a-f]+)", txt)
-        m_b = re.search(r"traffic-bytes-per-launch:\s*([0-9.eE+]+)", txt)
+        m_b = re.search(re.escape(key) + r":\s*([0-9.eE+-]+)", txt)
         if m_h and m_b and m_h.group(1) == kernel_hash():
             return float(m_b.group(1))
     return None
+
+
+def traffic_from_profiles(prec: str, workload: str):
+    """HBM bytes per tile-kernel launch (FETCH_SIZE / WRITE_SIZE summary)."""
+    return profile_value(prec, workload, "hbm_traffic", "traffic-bytes-per-launch")
 
 
 def issued_mfma_flops(prec: str, N: int, L: int) -> float:
@@ -195,17 +201,25 @@ def oracle_leg(x_np, outs, want_cpu, threads):
     return errs, cpu
 
 
-def raw_outputs(cl, torch, x, precs):
+TOL = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "bf16x4": 5e-4}
+
+
+def raw_outputs(cl, torch, x, precs, force=None):
     """Scores with the FP64 fix-up disabled (tolerance 0): the raw error of
-    the contraction + epilogue that the fix-up flag has to cover."""
-    tol = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "bf16x4": 5e-4}
+    the contraction + epilogue that the fix-up flag has to cover.  `force`:
+    {name: (products, schedule, band)} for names that run a forced
+    configuration of split-BF16."""
     outs = {}
-    for p in precs:
+    for name in precs:
+        p = "bf16" if force and name in force else name
         cl.set_tolerance(p, 0.0)
+        if force and name in force:
+            cl.force_config(*force[name])
         try:
-            outs[p + "_raw"] = cl.crmsd_matrix(x, p)
+            outs[name + "_raw"] = cl.crmsd_matrix(x, p)
         finally:
-            cl.set_tolerance(p, tol[p])
+            cl.set_tolerance(p, TOL[p])
+            cl.force_config(None)
     torch.cuda.synchronize()
     return outs
 
@@ -540,7 +554,11 @@ def main():
     torch.cuda.synchronize()
 
     prec = args.precision
-    log(f"[bench] {prec}: warmup {args.warmup}, steps {args.steps}")
+    # the kernel configuration the tuning table gives this size (split-BF16:
+    # three or four MFMA products per K-block)
+    kcfg = cl.get_config(N, L, prec)
+    iprec = "bf16x4" if prec == "bf16" and kcfg["products"] == 4 else prec
+    log(f"[bench] {prec}: kernel configuration {kcfg}; warmup {args.warmup}, steps {args.steps}")
     main_res, main_out = time_path(cl, torch, x, prec, args.steps, args.warmup)
     log(f"[bench] {prec}: {main_res}")
     outs = {prec: main_out}
@@ -560,6 +578,24 @@ def main():
         outs["fp32"] = cmp_out
     variants = {}
     if not args.no_compare and prec == "bf16":
+        # split-BF16 with the other product count than the table chose
+        other = 3 if kcfg["products"] == 4 else 4
+        name = f"bf16_x{other}"
+        force = {name: (other, kcfg["schedule"], kcfg["band"])}
+        steps = max(2, args.steps // 3)
+        log(f"[bench] {name}: split-BF16 forced to {other} products, steps {steps}")
+        cl.force_config(*force[name])
+        try:
+            vres, vout = time_path(cl, torch, x, "bf16", steps, 1)
+        finally:
+            cl.force_config(None)
+        vres["mfma_util"] = issued_mfma_flops("bf16x4" if other == 4 else "bf16", N, L) / (
+            vres["tile_ms"] * 1e-3) / (PEAK_TFLOPS["bf16"] * 1e12)
+        log(f"[bench] {name}: {vres}")
+        variants[name] = vres
+        outs[name] = vout
+        if not args.no_error:
+            outs.update(raw_outputs(cl, torch, x, [name], force))
         for vp in ("fp16", "bf16x4"):
             steps = max(2, args.steps // 3)
             log(f"[bench] {vp} variant: steps {steps}")
@@ -570,8 +606,9 @@ def main():
             variants[vp] = vres
             outs[vp] = vout
 
-    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
-                         else (os.cpu_count() or 1)))
+    # every host CPU this process may run on (the box's whole share)
+    threads = max(1, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                  else (os.cpu_count() or 1))
     extra = {}
     if not args.no_extra:
         log("[bench] config n5000_l300 (FP32 path at scale)")
@@ -607,10 +644,16 @@ def main():
     tile_s = main_res["tile_ms"] * 1e-3
     alg = 18.0 * L * P
     achieved = alg / tile_s / 1e12
-    issued = issued_mfma_flops(prec, N, L)
+    issued = issued_mfma_flops(iprec, N, L)
+    prof_ms = profile_value(iprec, args.workload, "kernel_trace", "avg-ms-per-launch")
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic_from_profiles(prec, args.workload),
-            "kernel": f"staged_kernel<{prec}>", "kernel_ms": main_res["tile_ms"],
+            "frac": achieved / PEAK_TFLOPS[prec],
+            "traffic": traffic_from_profiles(iprec, args.workload),
+            "kernel": f"staged_kernel<{iprec}>", "kernel_ms": main_res["tile_ms"],
+            # the same fraction from the committed rocprofv3 trace of this
+            # kernel (another box: box-to-box spread applies)
+            "profile_kernel_ms": prof_ms,
+            "profile_frac": (alg / (prof_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec]) if prof_ms else None,
             "issued_mfma_tflops": issued / tile_s / 1e12,
             "mfma_util": issued / tile_s / (PEAK_TFLOPS[prec] * 1e12),
             "effective_vs_fp32_peak": achieved / PEAK_TFLOPS["fp32"],
@@ -628,8 +671,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": prec, "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "L": L, "pairs": P,
-                   "precision": {"bf16": "split_bf16x3", "fp16": "split_fp16x3",
-                                 "fp32": "fp32"}[prec],
+                   "precision": {"bf16": f"split_bf16x{kcfg['products']}",
+                                 "fp16": "split_fp16x3", "fp32": "fp32"}[prec],
+                   "kernel_config": kcfg,
                    "epilogue": "fp64", "parallelism": "single_gpu"},
         "stages_ms": {k: main_res[k] for k in ("prep_ms", "tile_ms", "fixup_ms")},
         "fixup_blocks": main_res["fixup_blocks"],

@@ -99,6 +99,66 @@ clusco_status clusco_set_tolerance(clusco_handle h, clusco_precision p, double t
  * SPLIT_BF16, includes the dropped lo*lo' products; it is 0 for FP64. */
 clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L, double *eps);
 
+/* ------------------------------------------------------ kernel configuration
+ *
+ * How the covariance contraction of one problem runs (the arithmetic and the
+ * result's tolerance do not change with it; results may differ within the
+ * precision's tolerance between configurations).  The paper's workloads are
+ * decoy sets of very uneven size (Results and Discussion: 56 I-TASSER targets
+ * of 12,500 to 32,000 models, Table 1), so the configuration is chosen per
+ * (precision, N bucket, L bucket) from a tuning table measured on the device
+ * by paper_1302_4000_amd/tune.py:
+ *   products  split-BF16 only: 3 MFMA products per K-block (hi*hi' + hi*lo' +
+ *             lo*hi') or 4 (+ lo*lo').  Four products cost a third more MFMA
+ *             issue but leave far fewer pairs for the FP64 fix-up; the table
+ *             holds whichever made the whole call faster.  Other precisions
+ *             report 3 (4 for SPLIT_BF16X4).
+ *   schedule  CLUSCO_SCHED_STAGED: one 64x64 tile per 4-wave workgroup with
+ *             operands staged in LDS; CLUSCO_SCHED_PERSISTENT: persistent
+ *             8-wave workgroups alternating contraction and FP64 epilogue.
+ *             Backward and threshold calls always use the staged schedule; a
+ *             batched call uses the one most of its work prefers.
+ *   band      tile rows per band of the tile order (L2 reuse of operands).
+ * Without a table entry the built-in default is products 3, staged, band 16.
+ * A cross comparison of Na x Nb models takes the bucket of the all-vs-all
+ * size with as many pairs.
+ *
+ * The table is loaded by clusco_create from $CLUSCO_TUNING when that variable
+ * is set (an empty value: no table), else from tuning/<arch>.json in the
+ * directory of the library (arch from the device, e.g. gfx950); a missing or
+ * malformed file leaves the built-in defaults.  File format (JSON object):
+ *   "arch": "gfx950", "n_edges": [...], "l_edges": [...]  ascending lower
+ *   bucket bounds (bucket i: edges[i] <= x < edges[i+1], the last is open),
+ *   "entries": [{"precision": "fp32" | "split_bf16" | "split_fp16" |
+ *   "split_bf16x4", "n_bucket": i, "l_bucket": j, "products": 3 | 4,
+ *   "schedule": "staged" | "persistent", "band": 1..256, ...}]
+ * (other keys are ignored). */
+#define CLUSCO_SCHED_STAGED 0
+#define CLUSCO_SCHED_PERSISTENT 1
+
+typedef struct {
+    int32_t products; /* 3 or 4 (see above) */
+    int32_t schedule; /* CLUSCO_SCHED_STAGED or CLUSCO_SCHED_PERSISTENT */
+    int32_t band;     /* 1..256 */
+    int32_t source;   /* out: 0 built-in default, 1 tuning table, 2 forced */
+    int32_t bucket;   /* out: n_bucket * len(l_edges) + l_bucket of the table entry, else -1 */
+} clusco_config;
+
+/* Replace the handle's tuning table with the file at `path` (NULL: drop the
+ * table, back to the built-in default).  On error (CLUSCO_ERR_INVALID_ARG:
+ * unreadable or malformed; CLUSCO_ERR_UNSUPPORTED: made for another
+ * architecture) the table is unchanged.  Host only; no device work. */
+clusco_status clusco_load_tuning(clusco_handle h, const char *path);
+/* Path of the loaded table ("" if none).  Owned by the handle. */
+const char *clusco_tuning_path(clusco_handle h);
+/* The configuration calls with these sizes and precision will use. */
+clusco_status clusco_get_config(clusco_handle h, int64_t N, int64_t L, clusco_precision p,
+                                clusco_config *cfg);
+/* Use `cfg` (products, schedule, band) for every later call on this handle,
+ * whatever the table says; NULL returns to the table.  For measurement (the
+ * tuner times each candidate this way). */
+clusco_status clusco_force_config(clusco_handle h, const clusco_config *cfg);
+
 /* ----------------------------------------------------------- all-vs-all */
 
 /* Workspace bytes for clusco_crmsd_matrix with these sizes (0 if invalid). */

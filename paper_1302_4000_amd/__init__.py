@@ -10,11 +10,13 @@ from .binding import (Batch, ClucsoError, PRECISION, batched_workspace_size,  # 
                       crmsd_backward, crmsd_batched, crmsd_cross, crmsd_cross_backward,
                       cmo_matrix, cmo_workspace_size, crmsd_matrix, crmsd_threshold,
                       drmsd_matrix, drmsd_workspace_size,
-                      fixup_count, kmedoids, set_tolerance, workspace_size)
+                      fixup_count, force_config, get_config, kmedoids, load_tuning,
+                      set_tolerance, workspace_size)
 
 __all__ = ["Batch", "CRMSDCross", "CRMSDMatrix", "ClucsoError", "PRECISION",
            "batched_workspace_size", "crmsd_backward", "crmsd_batched", "crmsd_cross",
            "crmsd_cross_ad", "crmsd_cross_backward", "crmsd_matrix", "crmsd_matrix_ad",
            "crmsd_threshold", "drmsd_matrix", "drmsd_workspace_size", "kmedoids",
            "cmo_matrix", "cmo_workspace_size",
-           "fixup_count", "set_tolerance", "workspace_size"]
+           "fixup_count", "force_config", "get_config", "load_tuning", "set_tolerance",
+           "workspace_size"]

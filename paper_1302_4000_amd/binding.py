@@ -20,6 +20,21 @@ OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = range(5)
 PRECISION = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2, "fp64": 3,
              "bf16x4": 4, "split_bf16x4": 4}
 
+SCHEDULES = {"staged": 0, "persistent": 1}
+
+
+class Config(ctypes.Structure):
+    """clusco_config"""
+    _fields_ = [("products", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("band", ctypes.c_int32), ("source", ctypes.c_int32), ("bucket", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"products": self.products,
+                "schedule": {v: k for k, v in SCHEDULES.items()}.get(self.schedule, self.schedule),
+                "band": self.band, "source": ["default", "table", "forced"][self.source],
+                "bucket": self.bucket}
+
+
 _lib = None
 _lock = threading.Lock()
 _handles: dict[int, ctypes.c_void_p] = {}
@@ -59,6 +74,10 @@ def lib():
             "clusco_crmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_crmsd_matrix": (st, [vp, vp, i64, i64, st, vp, vp, sz, vp]),
             "clusco_crmsd_matrix_noalloc": (st, [vp, vp, i64, i64, st, vp, vp]),
+            "clusco_load_tuning": (st, [vp, ctypes.c_char_p]),
+            "clusco_tuning_path": (ctypes.c_char_p, [vp]),
+            "clusco_get_config": (st, [vp, i64, i64, st, ctypes.POINTER(Config)]),
+            "clusco_force_config": (st, [vp, ctypes.POINTER(Config)]),
             "clusco_drmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_cluster_workspace_size": (sz, [vp, i64, i32]),
             "clusco_cmo_workspace_size": (sz, [vp, i64, i64]),
@@ -153,6 +172,39 @@ def flag_epsilon(precision, L: int, device: int = 0) -> float:
     _check(lib().clusco_flag_epsilon(h, _prec(precision), int(L), ctypes.byref(e)), h,
            "clusco_flag_epsilon")
     return float(e.value)
+
+
+def load_tuning(path: str | None, device: int = 0):
+    """Replace the handle's tuning table with the JSON file at `path`
+    (None: drop it, back to the built-in default configuration)."""
+    h = handle(device)
+    _check(lib().clusco_load_tuning(h, path.encode() if path is not None else None), h,
+           "clusco_load_tuning")
+
+
+def tuning_path(device: int = 0) -> str:
+    return lib().clusco_tuning_path(handle(device)).decode()
+
+
+def get_config(N: int, L: int, precision="bf16", device: int = 0) -> dict:
+    """The kernel configuration calls with these sizes will use."""
+    h = handle(device)
+    c = Config()
+    _check(lib().clusco_get_config(h, int(N), int(L), _prec(precision), ctypes.byref(c)), h,
+           "clusco_get_config")
+    return c.as_dict()
+
+
+def force_config(products: int | None = None, schedule: str = "staged", band: int = 16,
+                 device: int = 0):
+    """Force one configuration for every later call (products None: back to
+    the tuning table)."""
+    h = handle(device)
+    if products is None:
+        _check(lib().clusco_force_config(h, None), h, "clusco_force_config")
+        return
+    c = Config(int(products), SCHEDULES[schedule], int(band), 0, -1)
+    _check(lib().clusco_force_config(h, ctypes.byref(c)), h, "clusco_force_config")
 
 
 def workspace_size(N: int, L: int, precision="fp32", device: int = 0) -> int:

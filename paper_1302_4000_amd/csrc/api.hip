@@ -3,6 +3,9 @@
 // before anything is enqueued.  Nothing on the per-call path allocates
 // device memory or synchronises the host; the first batched call for a new
 // shape uploads its plan (a small device table) once.
+#include <dlfcn.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -27,12 +30,39 @@ struct BatchPlan {
     int64_t total_models = 0, T = 0, n_wtiles = 0;
     size_t ws_total = 0, off_list = 0;
     Problem first{};          // any problem (for launches with one)
+    int sched = SCHED_STAGED;  // tile schedule of the launch
+    int emode = 0;             // kernel arithmetic (x4 when every problem is)
+    int mixed_x4 = 0;          // split-BF16 problems differ in their product count
     // cached graph for the last buffers it was captured with
     hipGraphExec_t exec = nullptr;
     const void *g_coords = nullptr, *g_out = nullptr, *g_ws = nullptr;
     // used inside a graph the caller captured: its table address is baked
     // into that graph, so the plan is kept until the handle is destroyed
     bool pinned = false;
+};
+
+// Kernel configuration of one problem: what the tuning table chooses per
+// (precision, N bucket, L bucket).
+struct KernelCfg {
+    int products = 3;               // split-BF16: MFMA products per K-block (3 or 4)
+    int schedule = SCHED_STAGED;    // SCHED_STAGED or SCHED_PERSISTENT
+    int band = 16;                  // tile rows per band of the tile order
+    int id = -1;                    // bucket index in the table (-1: not from the table)
+    int source = 0;                 // 0 built-in default, 1 tuning table, 2 forced
+};
+
+struct TuneEntry {
+    int mode, nb, lb;
+    KernelCfg cfg;
+};
+
+// Tuning table: bucket edges (ascending lower bounds; bucket i holds
+// edges[i] <= x < edges[i+1], the last one open) and the chosen
+// configuration per (precision, N bucket, L bucket).
+struct TuneTable {
+    std::vector<int64_t> n_edges, l_edges;
+    std::vector<TuneEntry> entries;
+    std::string path;
 };
 
 } // namespace
@@ -51,6 +81,13 @@ struct clusco_ctx {
     // point), looked up once per device when the handle is created
     void *scratch = nullptr;
     hipError_t scratch_err = hipSuccess;
+    // kernel configurations: tuning table, an optional forced configuration,
+    // and a generation count that changes with either (part of plan keys)
+    std::string arch;
+    TuneTable tune;
+    bool forced = false;
+    KernelCfg force;
+    int64_t tune_gen = 0;
 };
 
 // Built-in workspace of clusco_crmsd_matrix_noalloc: every device that loads
@@ -183,11 +220,295 @@ double contraction_eps(int mode, int64_t L)
 // Flag a pair when its score bound eps (E_i + E_j) / (L s) exceeds half the
 // tolerance, i.e. when s < flag_coef (E_i + E_j).  An unflagged pair's error
 // is then at most tol / (2 EPS_MARGIN) by the measured maxima.
-double flag_coef(clusco_handle h, int mode, int64_t L)
+double flag_coef(clusco_handle h, int mode, int64_t L, int arith_mode = -1)
 {
     const double tol = h->tol[mode];
     if (mode == MODE_FP64 || !(tol > 0.0)) return -1.0;
-    return 2.0 * contraction_eps(mode, L) / ((double)L * tol);
+    return 2.0 * contraction_eps(arith_mode < 0 ? mode : arith_mode, L) / ((double)L * tol);
+}
+
+// ---------------------------------------------------------------- tuning
+
+int bucket_of(const std::vector<int64_t> &edges, int64_t x)
+{
+    int b = 0;
+    for (size_t i = 1; i < edges.size(); ++i)
+        if (x >= edges[i]) b = (int)i;
+    return b;
+}
+
+// Configuration for a problem of N models (an all-vs-all ensemble, or the
+// all-vs-all size with as many pairs for a cross comparison) of L atoms.
+KernelCfg config_for(clusco_handle h, int mode, int64_t N, int64_t L)
+{
+    KernelCfg c;
+    if (h->forced) {
+        c = h->force;
+        c.source = 2;
+    } else if (!h->tune.n_edges.empty() && !h->tune.l_edges.empty()) {
+        const int nb = bucket_of(h->tune.n_edges, N), lb = bucket_of(h->tune.l_edges, L);
+        for (const TuneEntry &t : h->tune.entries) {
+            if (t.mode == mode && t.nb == nb && t.lb == lb) {
+                c = t.cfg;
+                c.id = nb * (int)h->tune.l_edges.size() + lb;
+                c.source = 1;
+                break;
+            }
+        }
+    }
+    if (mode != MODE_BF16) c.products = mode == MODE_BF16X4 ? 4 : 3;
+    return c;
+}
+
+// The arithmetic a problem's contraction uses: split-BF16 with four
+// products is the x4 mode.
+int arith_mode(int mode, const KernelCfg &c)
+{
+    return mode == MODE_BF16 && c.products == 4 ? MODE_BF16X4 : mode;
+}
+
+void apply_cfg(clusco_handle h, int mode, const KernelCfg &c, Problem &p)
+{
+    const int am = arith_mode(mode, c);
+    p.x4 = am == MODE_BF16X4;
+    p.band = c.band;
+    p.cfg = c.id;
+    p.flag_coef = flag_coef(h, mode, p.L, am);
+}
+
+// A minimal JSON reader for the tuning file (objects, arrays, strings,
+// numbers, true / false / null; nesting depth at most 32).
+struct JVal {
+    enum Kind { NUL, BOOL, NUM, STR, ARR, OBJ } kind = NUL;
+    double num = 0.0;
+    std::string str;
+    std::vector<JVal> arr;
+    std::vector<std::pair<std::string, JVal>> obj;
+    const JVal *get(const char *k) const
+    {
+        for (const auto &kv : obj)
+            if (kv.first == k) return &kv.second;
+        return nullptr;
+    }
+};
+
+struct JParser {
+    const char *p, *end;
+    std::string err;
+    void skip()
+    {
+        while (p < end && (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r')) ++p;
+    }
+    bool fail_at(const char *what)
+    {
+        if (err.empty()) err = what;
+        return false;
+    }
+    bool word(const char *w)
+    {
+        const size_t n = strlen(w);
+        if ((size_t)(end - p) < n || strncmp(p, w, n) != 0) return fail_at("bad literal");
+        p += n;
+        return true;
+    }
+    bool string(std::string &out)
+    {
+        if (p >= end || *p != '"') return fail_at("expected a string");
+        ++p;
+        while (p < end && *p != '"') {
+            if (*p == '\\') {
+                if (++p >= end) break;
+                const char c = *p;
+                if (c == 'u') {
+                    if (end - p < 5) return fail_at("bad escape");
+                    p += 4;
+                    out += '?';
+                } else {
+                    out += c == 'n' ? '\n' : c == 't' ? '\t' : c == 'r' ? '\r' : c == 'b' ? '\b' : c == 'f' ? '\f' : c;
+                }
+                ++p;
+            } else {
+                out += *p++;
+            }
+        }
+        if (p >= end) return fail_at("unterminated string");
+        ++p;
+        return true;
+    }
+    bool value(JVal &v, int depth)
+    {
+        if (depth > 32) return fail_at("nesting too deep");
+        skip();
+        if (p >= end) return fail_at("unexpected end");
+        const char c = *p;
+        if (c == '{') {
+            v.kind = JVal::OBJ;
+            ++p;
+            skip();
+            if (p < end && *p == '}') { ++p; return true; }
+            for (;;) {
+                skip();
+                std::string k;
+                if (!string(k)) return false;
+                skip();
+                if (p >= end || *p != ':') return fail_at("expected ':'");
+                ++p;
+                JVal x;
+                if (!value(x, depth + 1)) return false;
+                v.obj.emplace_back(std::move(k), std::move(x));
+                skip();
+                if (p < end && *p == ',') { ++p; continue; }
+                if (p < end && *p == '}') { ++p; return true; }
+                return fail_at("expected ',' or '}'");
+            }
+        }
+        if (c == '[') {
+            v.kind = JVal::ARR;
+            ++p;
+            skip();
+            if (p < end && *p == ']') { ++p; return true; }
+            for (;;) {
+                JVal x;
+                if (!value(x, depth + 1)) return false;
+                v.arr.push_back(std::move(x));
+                skip();
+                if (p < end && *p == ',') { ++p; continue; }
+                if (p < end && *p == ']') { ++p; return true; }
+                return fail_at("expected ',' or ']'");
+            }
+        }
+        if (c == '"') {
+            v.kind = JVal::STR;
+            return string(v.str);
+        }
+        if (c == 't') { v.kind = JVal::BOOL; v.num = 1; return word("true"); }
+        if (c == 'f') { v.kind = JVal::BOOL; return word("false"); }
+        if (c == 'n') return word("null");
+        char *q = nullptr;
+        std::string tok(p, (size_t)std::min<ptrdiff_t>(end - p, 64));
+        v.num = strtod(tok.c_str(), &q);
+        if (q == tok.c_str()) return fail_at("bad number");
+        v.kind = JVal::NUM;
+        p += q - tok.c_str();
+        return true;
+    }
+};
+
+int mode_of_name(const std::string &s)
+{
+    if (s == "fp32") return MODE_FP32;
+    if (s == "split_bf16") return MODE_BF16;
+    if (s == "split_fp16") return MODE_FP16;
+    if (s == "split_bf16x4") return MODE_BF16X4;
+    return -1;
+}
+
+bool read_edges(const JVal *v, std::vector<int64_t> &out)
+{
+    if (!v || v->kind != JVal::ARR || v->arr.empty() || v->arr.size() > 64) return false;
+    for (const JVal &x : v->arr) {
+        if (x.kind != JVal::NUM || x.num < 0 || x.num > 1e12 || x.num != std::floor(x.num))
+            return false;
+        if (!out.empty() && (int64_t)x.num <= out.back()) return false;
+        out.push_back((int64_t)x.num);
+    }
+    return true;
+}
+
+// Parses and checks a tuning file; on success *t holds it.  `arch` (may be
+// empty: not known) must match the file's "arch".
+clusco_status parse_tuning(const std::string &text, const std::string &arch, TuneTable *t,
+                           std::string *err)
+{
+    JParser jp{text.data(), text.data() + text.size(), {}};
+    JVal root;
+    if (!jp.value(root, 0)) {
+        *err = "tuning file: " + jp.err;
+        return CLUSCO_ERR_INVALID_ARG;
+    }
+    if (root.kind != JVal::OBJ) {
+        *err = "tuning file: not a JSON object";
+        return CLUSCO_ERR_INVALID_ARG;
+    }
+    const JVal *a = root.get("arch");
+    if (!a || a->kind != JVal::STR) {
+        *err = "tuning file: no \"arch\"";
+        return CLUSCO_ERR_INVALID_ARG;
+    }
+    if (!arch.empty() && a->str != arch) {
+        *err = "tuning file is for " + a->str + ", the device is " + arch;
+        return CLUSCO_ERR_UNSUPPORTED;
+    }
+    TuneTable out;
+    if (!read_edges(root.get("n_edges"), out.n_edges) || !read_edges(root.get("l_edges"), out.l_edges)) {
+        *err = "tuning file: n_edges / l_edges must be ascending non-negative integers";
+        return CLUSCO_ERR_INVALID_ARG;
+    }
+    const JVal *es = root.get("entries");
+    if (!es || es->kind != JVal::ARR) {
+        *err = "tuning file: no \"entries\" array";
+        return CLUSCO_ERR_INVALID_ARG;
+    }
+    for (const JVal &e : es->arr) {
+        const JVal *pr = e.get("precision"), *nb = e.get("n_bucket"), *lb = e.get("l_bucket"),
+                   *pd = e.get("products"), *sc = e.get("schedule"), *bd = e.get("band");
+        TuneEntry t{};
+        bool ok = e.kind == JVal::OBJ && pr && pr->kind == JVal::STR && nb && nb->kind == JVal::NUM &&
+                  lb && lb->kind == JVal::NUM && pd && pd->kind == JVal::NUM && sc &&
+                  sc->kind == JVal::STR && bd && bd->kind == JVal::NUM;
+        if (ok) {
+            t.mode = mode_of_name(pr->str);
+            t.nb = (int)nb->num;
+            t.lb = (int)lb->num;
+            t.cfg.products = (int)pd->num;
+            t.cfg.schedule = sc->str == "staged" ? SCHED_STAGED : sc->str == "persistent" ? SCHED_PERSISTENT : -1;
+            t.cfg.band = (int)bd->num;
+            ok = t.mode >= 0 && nb->num == t.nb && lb->num == t.lb && t.nb >= 0 &&
+                 t.nb < (int)out.n_edges.size() && t.lb >= 0 && t.lb < (int)out.l_edges.size() &&
+                 (t.cfg.products == 3 || t.cfg.products == 4) && t.cfg.schedule >= 0 &&
+                 bd->num == t.cfg.band && t.cfg.band >= 1 && t.cfg.band <= 256;
+        }
+        if (!ok) {
+            *err = "tuning file: bad entry (needs precision, n_bucket, l_bucket, products 3|4, "
+                   "schedule staged|persistent, band 1..256, buckets within the edges)";
+            return CLUSCO_ERR_INVALID_ARG;
+        }
+        out.entries.push_back(t);
+    }
+    *t = std::move(out);
+    return CLUSCO_OK;
+}
+
+clusco_status load_tuning_file(clusco_handle h, const std::string &path, std::string *err)
+{
+    FILE *f = fopen(path.c_str(), "rb");
+    if (!f) {
+        *err = "cannot open tuning file " + path;
+        return CLUSCO_ERR_INVALID_ARG;
+    }
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (16u << 20)) text.append(buf, n);
+    fclose(f);
+    TuneTable t;
+    const clusco_status st = parse_tuning(text, h->arch, &t, err);
+    if (st != CLUSCO_OK) return st;
+    t.path = path;
+    h->tune = std::move(t);
+    ++h->tune_gen;
+    return CLUSCO_OK;
+}
+
+// <directory of this library>/tuning/<arch>.json
+std::string default_tuning_path(const std::string &arch)
+{
+    Dl_info info{};
+    if (arch.empty() || !dladdr((void *)&default_tuning_path, &info) || !info.dli_fname) return "";
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.rfind('/');
+    const std::string dir = slash == std::string::npos ? "." : lib.substr(0, slash);
+    return dir + "/tuning/" + arch + ".json";
 }
 
 void stage_mark(clusco_handle h, int k, hipStream_t s)
@@ -247,6 +568,9 @@ Problem make_problem(const ModelSet &A, const ModelSet &B, int sym, double coef)
     p.XB = B.X;
     p.flag_coef = coef;
     p.sym = sym;
+    p.x4 = 0;
+    p.band = KernelCfg{}.band;
+    p.cfg = -1;
     return p;
 }
 
@@ -254,7 +578,20 @@ struct SingleLayout {
     ModelSet A, B;
     Problem p;
     size_t total, off_list;
+    KernelCfg cfg;
+    int emode;            // arithmetic of the contraction (x4 when chosen)
 };
+
+void configure(clusco_handle h, int mode, int64_t N, SingleLayout &s)
+{
+    if (!h) {
+        s.emode = mode;
+        return;
+    }
+    s.cfg = config_for(h, mode, N, s.p.L);
+    apply_cfg(h, mode, s.cfg, s.p);
+    s.emode = arith_mode(mode, s.cfg);
+}
 
 SingleLayout single_layout(clusco_handle h, int mode, int64_t N, int64_t L)
 {
@@ -262,19 +599,23 @@ SingleLayout single_layout(clusco_handle h, int mode, int64_t N, int64_t L)
     size_t o = 256;
     s.A = make_set(mode, 0, N, L, 0, 0, o);
     s.B = s.A;
-    s.p = make_problem(s.A, s.A, 1, h ? flag_coef(h, mode, L) : -1.0);
+    s.p = make_problem(s.A, s.A, 1, -1.0);
+    configure(h, mode, N, s);
     s.off_list = take(o, sizeof(FixEntry) * problem_wtiles(s.p));
     s.total = o;
     return s;
 }
 
+// A cross comparison takes the configuration of the all-vs-all size with as
+// many pairs.
 SingleLayout cross_layout(clusco_handle h, int mode, int64_t Na, int64_t Nb, int64_t L)
 {
     SingleLayout s{};
     size_t o = 256;
     s.A = make_set(mode, 0, Na, L, 0, 0, o);
     s.B = make_set(mode, 0, Nb, L, s.A.Np, 1, o);
-    s.p = make_problem(s.A, s.B, 0, h ? flag_coef(h, mode, L) : -1.0);
+    s.p = make_problem(s.A, s.B, 0, -1.0);
+    configure(h, mode, (int64_t)std::sqrt(2.0 * (double)Na * (double)Nb) + 1, s);
     s.off_list = take(o, sizeof(FixEntry) * problem_wtiles(s.p));
     s.total = o;
     return s;
@@ -411,6 +752,7 @@ clusco_status enqueue(clusco_handle h, int mode, const float *XA, const float *X
         fl.n_all = problem_wtiles(single->p);
         fl.list = tl.list;
         coef = single->p.flag_coef;
+        tl.sched = single->cfg.schedule;
     } else {
         pl.table = (const ModelSet *)plan->dtab;
         pl.nset = plan->nset;
@@ -426,13 +768,16 @@ clusco_status enqueue(clusco_handle h, int mode, const float *XA, const float *X
         fl.n_all = plan->n_wtiles;
         fl.list = tl.list;
         coef = plan->first.flag_coef;
+        tl.sched = plan->sched;
+        tl.mixed_x4 = plan->mixed_x4;
     }
+    const int emode = single ? single->emode : plan->emode;
     if (timing) stage_mark(h, 0, s);
     hipError_t e = launch_prep(pl, s);
     if (e != hipSuccess) return hip_fail(h, e, "prep launch");
     if (timing) stage_mark(h, 1, s);
     if (mode != MODE_FP64) {
-        e = launch_tile(mode, tl, s);
+        e = launch_tile(emode, tl, s);
         if (e != hipSuccess) return hip_fail(h, e, "tile launch");
     }
     if (timing) stage_mark(h, 2, s);
@@ -456,6 +801,7 @@ std::vector<int64_t> batch_key(clusco_handle h, int mode, const BatchInput &b, b
     std::vector<int64_t> k;
     k.reserve(4 * b.E + 4);
     k.push_back(mode);
+    k.push_back(h->tune_gen);
     k.push_back(b.E);
     double tol = h->tol[mode];
     int64_t t;
@@ -475,27 +821,46 @@ std::vector<int64_t> batch_key(clusco_handle h, int mode, const BatchInput &b, b
 // Host-side plan: sets in input order, problems sorted by cost per tile
 // (padded length, then size) so the persistent kernel starts the longest
 // tiles first.  Returns the workspace size; fills tables when asked.
+struct PlanKernel {
+    int sched = SCHED_STAGED, emode = 0, mixed_x4 = 0;
+};
+
 size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<ModelSet> *sets,
                    std::vector<Problem> *probs, size_t *off_list, int64_t *T, int64_t *nw,
-                   int64_t *total)
+                   int64_t *total, PlanKernel *pk = nullptr)
 {
     size_t o = 256;
     std::vector<ModelSet> S;
     std::vector<Problem> P;
     int64_t model0 = 0;
+    // each problem takes its bucket's configuration; the launch takes the
+    // schedule that most of the work (tiles x K-blocks x products) prefers
+    double vote[2] = {0.0, 0.0};
+    int nx4 = 0;
     for (int32_t e = 0; e < b.E; ++e) {
         if (b.N[e] < 2) continue;
         ModelSet s = make_set(mode, b.coff ? b.coff[e] : 0, b.N[e], b.L[e], model0, 0, o);
         model0 += s.Np;
         S.push_back(s);
-        Problem p = make_problem(s, s, 1, flag_coef(h, mode, b.L[e]));
+        Problem p = make_problem(s, s, 1, -1.0);
+        const KernelCfg c = config_for(h, mode, b.N[e], b.L[e]);
+        apply_cfg(h, mode, c, p);
         p.out = b.ooff ? b.ooff[e] : 0;
+        nx4 += p.x4;
+        vote[c.schedule == SCHED_PERSISTENT] +=
+            (double)problem_tiles(p) * (double)p.KB * (p.x4 ? 4.0 : 3.0);
         P.push_back(p);
     }
     std::stable_sort(P.begin(), P.end(), [](const Problem &x, const Problem &y) {
-        if (x.KB != y.KB) return x.KB > y.KB;
+        const int64_t cx = x.KB * (x.x4 ? 4 : 3), cy = y.KB * (y.x4 ? 4 : 3);
+        if (cx != cy) return cx > cy;
         return x.NA > y.NA;
     });
+    if (pk) {
+        pk->sched = vote[1] > vote[0] ? SCHED_PERSISTENT : SCHED_STAGED;
+        pk->emode = (nx4 > 0 && nx4 == (int)P.size()) ? MODE_BF16X4 : mode;
+        pk->mixed_x4 = nx4 > 0 && nx4 < (int)P.size();
+    }
     int64_t t0 = 0, w0 = 0;
     for (Problem &p : P) {
         p.tile0 = t0;
@@ -542,8 +907,12 @@ clusco_status create_plan(clusco_handle h, int mode, const BatchInput &b,
     p.key = std::move(key);
     std::vector<ModelSet> sets;
     std::vector<Problem> probs;
+    PlanKernel pk;
     p.ws_total = plan_layout(h, mode, b, &sets, &probs, &p.off_list, &p.T, &p.n_wtiles,
-                             &p.total_models);
+                             &p.total_models, &pk);
+    p.sched = pk.sched;
+    p.emode = pk.emode;
+    p.mixed_x4 = pk.mixed_x4;
     p.nset = (int32_t)sets.size();
     p.nprob = (int32_t)probs.size();
     if (p.nprob > 0) {
@@ -619,9 +988,80 @@ clusco_status clusco_create(clusco_handle *h, int device)
     {
         DeviceGuard g(device);
         c->scratch_err = g.err != hipSuccess ? g.err : scratch_setup(device, &c->scratch);
+        hipDeviceProp_t prop;
+        if (g.err == hipSuccess && hipGetDeviceProperties(&prop, device) == hipSuccess) {
+            c->arch = prop.gcnArchName;
+            const size_t colon = c->arch.find(':');
+            if (colon != std::string::npos) c->arch.resize(colon);
+        }
+    }
+    // the tuning table: $CLUSCO_TUNING if set (empty: none), else the file
+    // for this architecture next to the library; without one (or if it does
+    // not parse) every problem takes the built-in default configuration
+    const char *env = getenv("CLUSCO_TUNING");
+    const std::string path = env ? std::string(env) : default_tuning_path(c->arch);
+    if (!path.empty()) {
+        std::string err;
+        (void)load_tuning_file(c, path, &err);
     }
     *h = c;
     return CLUSCO_OK;
+}
+
+clusco_status clusco_load_tuning(clusco_handle h, const char *path)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!path) {
+        h->tune = TuneTable{};
+        ++h->tune_gen;
+        return CLUSCO_OK;
+    }
+    std::string err;
+    const clusco_status st = load_tuning_file(h, path, &err);
+    return st == CLUSCO_OK ? st : fail(h, st, err.c_str());
+}
+
+clusco_status clusco_get_config(clusco_handle h, int64_t N, int64_t L, clusco_precision p,
+                                clusco_config *cfg)
+{
+    if (!h || !cfg) return CLUSCO_ERR_INVALID_ARG;
+    if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
+    if (N < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0 and L >= 1");
+    const KernelCfg c = config_for(h, mode_of(p), N, L);
+    cfg->products = c.products;
+    cfg->schedule = c.schedule;
+    cfg->band = c.band;
+    cfg->source = c.source;
+    cfg->bucket = c.id;
+    return CLUSCO_OK;
+}
+
+clusco_status clusco_force_config(clusco_handle h, const clusco_config *cfg)
+{
+    if (!h) return CLUSCO_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!cfg) {
+        h->forced = false;
+    } else {
+        if ((cfg->products != 3 && cfg->products != 4) ||
+            (cfg->schedule != CLUSCO_SCHED_STAGED && cfg->schedule != CLUSCO_SCHED_PERSISTENT) ||
+            cfg->band < 1 || cfg->band > 256)
+            return fail(h, CLUSCO_ERR_INVALID_ARG,
+                        "need products 3 or 4, a known schedule and band in 1..256");
+        h->forced = true;
+        h->force = KernelCfg{};
+        h->force.products = cfg->products;
+        h->force.schedule = cfg->schedule;
+        h->force.band = cfg->band;
+    }
+    ++h->tune_gen;
+    return CLUSCO_OK;
+}
+
+const char *clusco_tuning_path(clusco_handle h)
+{
+    return h ? h->tune.path.c_str() : "";
 }
 
 void clusco_destroy(clusco_handle h)
@@ -1086,7 +1526,7 @@ clusco_status clusco_crmsd_threshold(clusco_handle h, const float *coords, int64
         tl.counters = (int *)w;
         tl.list = (FixEntry *)(w + t.s.off_list);
         tl.emit = em;
-        e = launch_tile(mode, tl, st, OP_THR);
+        e = launch_tile(t.s.emode, tl, st, OP_THR);
         if (e != hipSuccess) return hip_fail(h, e, "threshold tile launch");
         stage_mark(h, 2, st);
         if (t.s.p.flag_coef > 0.0) {

@@ -154,7 +154,16 @@ struct Problem {
     int64_t out;          // float offset into the output base
     double flag_coef;     // flag a pair when score < flag_coef (E_i + E_j); <= 0 never
     int32_t sym;          // 1: all-vs-all (packed, i < j); 0: dense NA x NB
-    int32_t pad;
+    // kernel configuration chosen for this problem's (N, L) bucket
+    int32_t x4;           // split-BF16: the fourth product lo*lo' is issued too
+    int32_t band;         // tile rows per band of the tile order
+    int32_t cfg;          // bucket of the tuning table the choice came from (-1: default)
+};
+
+// Tile schedules (a tuning choice per problem bucket).
+enum Schedule {
+    SCHED_STAGED = 0,      // one 64x64 tile per 4-wave workgroup, operands staged in LDS
+    SCHED_PERSISTENT = 1   // persistent 8-wave workgroups, contraction / epilogue ping-pong
 };
 
 __host__ __device__ inline int64_t problem_tiles(const Problem &p)
@@ -209,6 +218,8 @@ struct TileLaunch {
     int32_t nprob;
     int32_t kind;         // TK_SYM, TK_RECT, TK_BATCH
     int64_t T;            // 64x64 tiles in the launch
+    int32_t sched;        // SCHED_STAGED or SCHED_PERSISTENT (forward only)
+    int32_t mixed_x4;     // TK_BATCH split-BF16: problems differ in x4
     int *counters;
     FixEntry *list;
     // backward pass only: forward scores, incoming gradients, and the per-pair

@@ -15,7 +15,14 @@
 //            wave below the diagonal of a diagonal tile idles);
 //  TK_RECT   one cross comparison, every tile of the NA x NB grid;
 //  TK_BATCH  many all-vs-all ensembles in one launch.
-// The kernel is persistent with a ping-pong schedule; see tile_kernel.
+// Two schedules, chosen per problem bucket by the tuning table: the staged
+// kernel (one tile per 4-wave workgroup, operands staged in LDS; see
+// staged_kernel) and the persistent ping-pong kernel (see tile_kernel).
+// The order of tiles within a problem is banded (band_decode) with the
+// problem's band width: a band's column sweep re-reads the column operands
+// once per band, so wider bands fetch less until the band's row operands and
+// the columns in flight outgrow the XCD's 4 MB L2 (at N = 20,000, L = 150,
+// split-BF16: 8 rows fetched 0.77 GB per launch, 16 rows 0.44 GB).
 #include "eq2.h"
 #include "internal.h"
 
@@ -42,10 +49,22 @@ __device__ __forceinline__ f32x16 mfma_split(u32x4 a, u32x4 b, f32x16 c)
                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
+// Whether the split-BF16 contraction of problem p issues the fourth product
+// lo*lo': always in the x4 mode; in a batch of split-BF16 problems per
+// problem (the tuning table chooses three or four products per bucket).
+template <int MODE, int KIND>
+__device__ __forceinline__ bool issue_lolo(const TileLaunch &a, const Problem &p)
+{
+    if constexpr (MODE == MODE_BF16X4) return true;
+    else if constexpr (MODE == MODE_BF16 && KIND == TK_BATCH) return a.mixed_x4 && p.x4;
+    else return false;
+}
+
 // Contraction of one 32x32 wave tile: acc[3c+d] += X_c[Ra rows] X_d[Rb rows]^T
 template <int MODE>
 __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int64_t Ra,
-                                         int64_t Rb, int64_t KB, int lane, f32x16 acc[9])
+                                         int64_t Rb, int64_t KB, int lane, bool lolo,
+                                         f32x16 acc[9])
 {
     if constexpr (MODE == MODE_FP32) {
         const f32x4 *pa = (const f32x4 *)opsA + Ra * KB * 3 * 64 + lane;
@@ -119,7 +138,7 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
                     acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
-            if constexpr (MODE == MODE_BF16X4) {
+            if (lolo) {
                 // fourth product lo*lo': the split then carries no dropped term
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -159,13 +178,6 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
 #define EPI_STEPS 3
 #endif
 
-// Tile rows per band of the launch order.  A band's column sweep re-reads
-// the column operands once per band, so wider bands fetch less, until the
-// band's row operands and the columns in flight outgrow the XCD's 4 MB L2:
-// at N = 20,000, L = 150 (split-BF16) 8 rows fetched 0.77 GB per launch,
-// 16 rows 0.44 GB (and ran 4% faster), 32 rows 3.8 GB.
-constexpr int64_t BAND = 16;
-
 // A wave's share of one 64x64 tile: its 32x32 block and the problem.
 struct WaveJob {
     int64_t Ra, Rb;
@@ -191,11 +203,11 @@ __device__ __forceinline__ WaveJob decode_job(const TileLaunch &a, int64_t t, in
     int32_t e = 0;
     if constexpr (KIND == TK_BATCH) {
         e = table_find(a.table, a.nprob, t, [](const Problem &q) { return q.tile0; });
-        tri_decode(t - a.table[e].tile0, a.table[e].nbA, &bi, &bj);
+        band_decode(t - a.table[e].tile0, a.table[e].nbA, a.table[e].band, &bi, &bj);
     } else if constexpr (KIND == TK_SYM) {
-        band_decode(t, a.prob.nbA, BAND, &bi, &bj);
+        band_decode(t, a.prob.nbA, a.prob.band, &bi, &bj);
     } else {
-        band_decode_rect(t, a.prob.nbA, a.prob.nbB, BAND, &bi, &bj);
+        band_decode_rect(t, a.prob.nbA, a.prob.nbB, a.prob.band, &bi, &bj);
     }
     const Problem &p = problem_of<KIND>(a, e);
     const int wy = w >> 1, wx = w & 1;
@@ -488,7 +500,8 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
                 const Problem &p = problem_of<KIND>(a, job.pidx);
-                contract<MODE>(a.ws + p.opsA, a.ws + p.opsB, job.Ra, job.Rb, p.KB, lane, acc);
+                contract<MODE>(a.ws + p.opsA, a.ws + p.opsB, job.Ra, job.Rb, p.KB, lane,
+                               issue_lolo<MODE, KIND>(a, p), acc);
             }
         } else if (job.active) {
             const Problem &pe = problem_of<KIND>(a, job.pidx);
@@ -571,21 +584,34 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wy = w >> 1, wx = w & 1;
-    // tiles in banded order, one contiguous chunk per XCD (workgroups are
-    // dealt to the XCDs round-robin)
-    const int64_t per_xcd = gridDim.x >> 3;
-    const int64_t t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    // Workgroups are dealt to the XCDs round-robin.  One problem: tiles in
+    // banded order, one contiguous chunk per XCD.  A batch: the host's order
+    // (most expensive tiles first, for balance) in runs of eight consecutive
+    // tiles per XCD (within every 64 workgroups, XCD x takes tiles 8x..8x+7),
+    // so neighbouring tiles of one problem share an L2.
+    int64_t t;
+    if constexpr (KIND == TK_BATCH) {
+        const int64_t b = blockIdx.x;
+        t = (b & ~(int64_t)63) + 8 * (b & 7) + ((b >> 3) & 7);
+    } else {
+        const int64_t per_xcd = gridDim.x >> 3;
+        t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    }
     if (t >= a.T) return;                          // uniform over the workgroup
-    const Problem &p = a.prob;
+    int32_t e = 0;
+    if constexpr (KIND == TK_BATCH)
+        e = table_find(a.table, a.nprob, t, [](const Problem &q) { return q.tile0; });
+    const Problem &p = problem_of<KIND>(a, e);
     int64_t bi, bj;
-    if constexpr (KIND == TK_SYM) band_decode(t, p.nbA, BAND, &bi, &bj);
-    else band_decode_rect(t, p.nbA, p.nbB, BAND, &bi, &bj);
+    if constexpr (KIND == TK_RECT) band_decode_rect(t, p.nbA, p.nbB, p.band, &bi, &bj);
+    else band_decode(t - p.tile0, p.nbA, p.band, &bi, &bj);
     const int64_t KB = p.KB;
+    const bool lolo = issue_lolo<MODE, KIND>(a, p);
 
     WaveJob job;
     job.Ra = 2 * bi + wy;
     job.Rb = 2 * bj + wx;
-    job.pidx = 0;
+    job.pidx = e;
     job.active = !(p.sym && bi == bj && wy > wx) && job.Ra * ROWBLK < p.NA &&
                  job.Rb * ROWBLK < p.NB;
     // the epilogue's radii, loaded with the first K-blocks
@@ -661,7 +687,7 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
                     acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
-            if constexpr (MODE == MODE_BF16X4) {
+            if (lolo) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -723,7 +749,9 @@ template <int MODE>
 static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, int op)
 {
     dim3 g((unsigned)grid), b(512);
-    const dim3 sg((unsigned)round_up(a.T > 0 ? a.T : 1, 8)), sb(256);
+    // staged grids: a multiple of 8 (one chunk per XCD), or of 64 for a batch
+    // (runs of 8 tiles per XCD); workgroups past the last tile return at once
+    const dim3 sg((unsigned)round_up(a.T > 0 ? a.T : 1, a.kind == TK_BATCH ? 64 : 8)), sb(256);
     if (op == OP_THR) {
         if (a.kind != TK_SYM) return hipErrorInvalidValue;
         staged_kernel<MODE, TK_SYM, OP_THR><<<sg, sb, 0, s>>>(a);
@@ -735,14 +763,21 @@ static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, 
         else return hipErrorInvalidValue;
         return hipGetLastError();
     }
+    const bool pers = a.sched == SCHED_PERSISTENT;
     switch (a.kind) {
     case TK_SYM:
-    case TK_RECT: {
-        if (a.kind == TK_SYM) staged_kernel<MODE, TK_SYM, OP_FWD><<<sg, sb, 0, s>>>(a);
+        if (pers) tile_kernel<MODE, TK_SYM, OP_FWD><<<g, b, 0, s>>>(a);
+        else staged_kernel<MODE, TK_SYM, OP_FWD><<<sg, sb, 0, s>>>(a);
+        break;
+    case TK_RECT:
+        if (pers) tile_kernel<MODE, TK_RECT, OP_FWD><<<g, b, 0, s>>>(a);
         else staged_kernel<MODE, TK_RECT, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
-    }
-    default: tile_kernel<MODE, TK_BATCH, OP_FWD><<<g, b, 0, s>>>(a); break;
+    case TK_BATCH:
+        if (pers) tile_kernel<MODE, TK_BATCH, OP_FWD><<<g, b, 0, s>>>(a);
+        else staged_kernel<MODE, TK_BATCH, OP_FWD><<<sg, sb, 0, s>>>(a);
+        break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
