@@ -91,12 +91,17 @@ const char *clusco_last_error(clusco_handle h);
 clusco_status clusco_set_tolerance(clusco_handle h, clusco_precision p, double tol);
 
 /* The error model behind the fix-up (derived from Eq. 2: an error d of the
- * contraction moves L cRMSD^2 by 2d).  For precision p and models of L atoms,
- * *eps is the relative contraction error the library assumes: the score s of
- * a pair with radii E_i = L R_i^2, E_j is trusted when
- * eps (E_i + E_j) / (L s) <= tol / 2 and recomputed in FP64 otherwise.  eps
- * grows with the FP32 accumulation steps (sqrt of the padded length) and, for
- * SPLIT_BF16, includes the dropped lo*lo' products; it is 0 for FP64. */
+ * correlation moves L cRMSD^2 by 2d).  For precision p and models of L atoms,
+ * *eps is the relative contraction error the library assumes: with W_i the
+ * squared size of what the MFMAs contracted for model i (sum of squared
+ * residuals from the reference in the reference frame, else its radius
+ * E_i = L R_i^2), the score s of a pair is trusted when
+ *     (eps (W_i + W_j) + 2e-10 (E_i + E_j)) / (L s) <= tol / 2
+ * (the second term bounds the FP64 epilogue's root finding) and recomputed
+ * in FP64 otherwise.  eps grows with the FP32 accumulation steps (sqrt of
+ * the padded length) and, for three-product SPLIT_BF16, includes the dropped
+ * lo*lo' products (use SPLIT_BF16X4 for the four-product value); it is 0 for
+ * FP64. */
 clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L, double *eps);
 
 /* ------------------------------------------------------ kernel configuration
@@ -119,7 +124,17 @@ clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L
  *             Backward and threshold calls always use the staged schedule; a
  *             batched call uses the one most of its work prefers.
  *   band      tile rows per band of the tile order (L2 reuse of operands).
- * Without a table entry the built-in default is products 3, staged, band 16.
+ *   frame     1: every model is first superimposed onto a reference structure
+ *             (the first model of the ensemble; of set A in a cross
+ *             comparison) by its optimal rotation, and the MFMA contraction
+ *             runs on the residuals from the reference; the large per-model
+ *             terms of the correlation are added back in FP64.  Rotating a
+ *             model leaves its scores unchanged (Eq. 1), while the
+ *             contraction error shrinks with the residuals' size, so far
+ *             fewer pairs need the FP64 fix-up.  0: the centred models are
+ *             contracted directly.  FP64 and the backward never use it.
+ * Without a table entry the built-in default is products 3, staged, band 16,
+ * frame 1.
  * A cross comparison of Na x Nb models takes the bucket of the all-vs-all
  * size with as many pairs.
  *
@@ -131,7 +146,8 @@ clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L
  *   bucket bounds (bucket i: edges[i] <= x < edges[i+1], the last is open),
  *   "entries": [{"precision": "fp32" | "split_bf16" | "split_fp16" |
  *   "split_bf16x4", "n_bucket": i, "l_bucket": j, "products": 3 | 4,
- *   "schedule": "staged" | "persistent", "band": 1..256, ...}]
+ *   "schedule": "staged" | "persistent", "band": 1..256, optionally
+ *   "frame": 0 | 1 (default 1), ...}]
  * (other keys are ignored). */
 #define CLUSCO_SCHED_STAGED 0
 #define CLUSCO_SCHED_PERSISTENT 1
@@ -140,6 +156,7 @@ typedef struct {
     int32_t products; /* 3 or 4 (see above) */
     int32_t schedule; /* CLUSCO_SCHED_STAGED or CLUSCO_SCHED_PERSISTENT */
     int32_t band;     /* 1..256 */
+    int32_t frame;    /* 1: contract residuals in the reference frame, 0: the models */
     int32_t source;   /* out: 0 built-in default, 1 tuning table, 2 forced */
     int32_t bucket;   /* out: n_bucket * len(l_edges) + l_bucket of the table entry, else -1 */
 } clusco_config;

@@ -26,13 +26,14 @@ SCHEDULES = {"staged": 0, "persistent": 1}
 class Config(ctypes.Structure):
     """clusco_config"""
     _fields_ = [("products", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("band", ctypes.c_int32), ("source", ctypes.c_int32), ("bucket", ctypes.c_int32)]
+                ("band", ctypes.c_int32), ("frame", ctypes.c_int32), ("source", ctypes.c_int32),
+                ("bucket", ctypes.c_int32)]
 
     def as_dict(self):
         return {"products": self.products,
                 "schedule": {v: k for k, v in SCHEDULES.items()}.get(self.schedule, self.schedule),
-                "band": self.band, "source": ["default", "table", "forced"][self.source],
-                "bucket": self.bucket}
+                "band": self.band, "frame": self.frame,
+                "source": ["default", "table", "forced"][self.source], "bucket": self.bucket}
 
 
 _lib = None
@@ -196,14 +197,14 @@ def get_config(N: int, L: int, precision="bf16", device: int = 0) -> dict:
 
 
 def force_config(products: int | None = None, schedule: str = "staged", band: int = 16,
-                 device: int = 0):
+                 frame: int = 1, device: int = 0):
     """Force one configuration for every later call (products None: back to
     the tuning table)."""
     h = handle(device)
     if products is None:
         _check(lib().clusco_force_config(h, None), h, "clusco_force_config")
         return
-    c = Config(int(products), SCHEDULES[schedule], int(band), 0, -1)
+    c = Config(int(products), SCHEDULES[schedule], int(band), int(frame), 0, -1)
     _check(lib().clusco_force_config(h, ctypes.byref(c)), h, "clusco_force_config")
 
 

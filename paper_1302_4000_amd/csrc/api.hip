@@ -30,9 +30,10 @@ struct BatchPlan {
     int64_t total_models = 0, T = 0, n_wtiles = 0;
     size_t ws_total = 0, off_list = 0;
     Problem first{};          // any problem (for launches with one)
-    int sched = SCHED_STAGED;  // tile schedule of the launch
+    int sched = SCHED_STAGED;  // tile schedule of the launches
     int emode = 0;             // kernel arithmetic (x4 when every problem is)
-    int mixed_x4 = 0;          // split-BF16 problems differ in their product count
+    int64_t T4 = 0;            // split-BF16: tiles of the four-product problems (they
+                               // come first and take a launch of their own)
     // cached graph for the last buffers it was captured with
     hipGraphExec_t exec = nullptr;
     const void *g_coords = nullptr, *g_out = nullptr, *g_ws = nullptr;
@@ -47,6 +48,7 @@ struct KernelCfg {
     int products = 3;               // split-BF16: MFMA products per K-block (3 or 4)
     int schedule = SCHED_STAGED;    // SCHED_STAGED or SCHED_PERSISTENT
     int band = 16;                  // tile rows per band of the tile order
+    int frame = 1;                  // contract residuals in the reference frame
     int id = -1;                    // bucket index in the table (-1: not from the table)
     int source = 0;                 // 0 built-in default, 1 tuning table, 2 forced
 };
@@ -182,28 +184,34 @@ struct DeviceGuard {
 // Error model of the contraction, the basis of the FP64 fix-up flag.
 //
 // Eq. 2 gives L s^2 = E_i + E_j - 2 S(H), S the signed sum of the singular
-// values of H.  An error dH of the contraction moves S by at most about
-// |dH| and hence the score s by d(L s^2) / (2 L s).  Writing the error of
-// S as eps (E_i + E_j) / 2 bounds the score error by
-//     err(s) <= eps (E_i + E_j) / (L s),
-// which grows without bound as s -> 0: small scores need the fix-up.  eps
+// values of H.  An error dH of the correlation moves S by at most about |dH|
+// and hence the score s by d(L s^2) / (2 L s).  The correlation's error comes
+// from the low-precision contraction of the vectors the MFMAs see (the
+// centred models, or in the reference frame their residuals d from the
+// reference), whose squared size is W = sum |d|^2 (W = E without the frame),
+// plus the FP64 epilogue's own error, relative to S itself (of the size of
+// the radii E).  Writing them as eps_W (W_i + W_j) / 2 and
+// eps_E (E_i + E_j) / 2 bounds the score error by
+//     err(s) <= (eps_W (W_i + W_j) + eps_E (E_i + E_j)) / (L s),
+// which grows without bound as s -> 0: small scores need the fix-up.  eps_W
 // has two measured parts:
 //   accumulation  every MFMA step rounds the FP32 accumulators once, so an
-//                 accumulator that grows steadily to about E carries about
-//                 2^-24 E sqrt(steps / 3) of rounding (a random walk over
+//                 accumulator that grows steadily to about W carries about
+//                 2^-24 W sqrt(steps / 3) of rounding (a random walk over
 //                 the steps): steps = Lp/2 (FP32, 2 atoms per step),
 //                 3 Lp/16 (split, 16 atoms per product, three products) or
 //                 4 Lp/16 (split x4);
-//   dropped term  split-BF16 x3 leaves out lo*lo' (|lo| <= 2^-9 |a|): per
-//                 atom a product of about 2^-18 |a||b| with a random sign,
-//                 2^-18 E / sqrt(L) summed (split-FP16 x3 drops 2^-24 |a||b|,
+//   dropped term  split-BF16 x3 leaves out lo*lo' (|lo| <= 2^-9 |d|): per
+//                 atom a product of about 2^-18 |d||d'| with a random sign,
+//                 2^-18 W / sqrt(L) summed (split-FP16 x3 drops 2^-24 |d||d'|,
 //                 which the accumulation part covers; x4 drops nothing).
-// The epilogue's unrefined hardware reciprocal square roots (relative error
-// below 6e-8) add R_RSQ.  The coefficients are fitted to GPU measurements of
-// max err s L / (E_i + E_j) with the fix-up off (FP64 oracle, L = 150, 300
-// and 500); EPS_MARGIN keeps every measured maximum at most 1 / EPS_MARGIN
-// of the model's value.
-constexpr double K_ACC = 0.70, K_DROP = 1.90, R_RSQ = 6e-8, EPS_MARGIN = 1.5;
+// The coefficients are fitted to GPU measurements of max err s L / (W_i + W_j)
+// with the fix-up off (FP64 oracle, L = 150, 300 and 500); EPS_MARGIN keeps
+// every measured maximum at most 1 / EPS_MARGIN of the model's value.
+// eps_E covers the epilogue's largest root (Newton steps stop below 1e-5
+// relative change: the root is then good to about 1e-10) with a margin of two;
+// the refined reciprocal square roots and FP64 rounding add about 1e-15.
+constexpr double K_ACC = 0.70, K_DROP = 1.90, EPS_MARGIN = 1.5, EPS_ROOT = 2e-10;
 
 double contraction_eps(int mode, int64_t L)
 {
@@ -214,17 +222,30 @@ double contraction_eps(int mode, int64_t L)
                                                : 3.0 * Lp / 16.0;
     const double acc = std::ldexp(1.0, -24) * std::sqrt(steps / 3.0);
     const double drop = mode == MODE_BF16 ? std::ldexp(1.0, -18) / std::sqrt((double)L) : 0.0;
-    return EPS_MARGIN * (K_ACC * acc + K_DROP * drop + R_RSQ);
+    return EPS_MARGIN * (K_ACC * acc + K_DROP * drop);
 }
 
-// Flag a pair when its score bound eps (E_i + E_j) / (L s) exceeds half the
-// tolerance, i.e. when s < flag_coef (E_i + E_j).  An unflagged pair's error
-// is then at most tol / (2 EPS_MARGIN) by the measured maxima.
-double flag_coef(clusco_handle h, int mode, int64_t L, int arith_mode = -1)
+// Flag a pair when its score bound exceeds half the tolerance, i.e. when
+// s < F_i + F_j with the per-model flag weight F = fw W + fe E,
+// fw = 2 eps_W / (L tol), fe = 2 eps_E / (L tol).  An unflagged pair's error
+// is then at most tol / (2 EPS_MARGIN) by the measured maxima.  tol is the
+// requested precision's; eps_W is the arithmetic's (split-BF16 with four
+// products has its own).
+struct FlagCoefs {
+    double fw = 0.0, fe = 0.0;
+    bool on = false;
+};
+
+FlagCoefs flag_coefs(clusco_handle h, int mode, int arith, int64_t L)
 {
-    const double tol = h->tol[mode];
-    if (mode == MODE_FP64 || !(tol > 0.0)) return -1.0;
-    return 2.0 * contraction_eps(arith_mode < 0 ? mode : arith_mode, L) / ((double)L * tol);
+    FlagCoefs f;
+    const double tol = h ? h->tol[mode] : 0.0;
+    if (mode == MODE_FP64 || !(tol > 0.0)) return f;
+    const double k = 2.0 / ((double)L * tol);
+    f.fw = k * contraction_eps(arith, L);
+    f.fe = k * EPS_ROOT;
+    f.on = true;
+    return f;
 }
 
 // ---------------------------------------------------------------- tuning
@@ -257,6 +278,8 @@ KernelCfg config_for(clusco_handle h, int mode, int64_t N, int64_t L)
         }
     }
     if (mode != MODE_BF16) c.products = mode == MODE_BF16X4 ? 4 : 3;
+    // the persistent schedule serves problems without the reference frame
+    if (mode == MODE_FP64 || c.schedule == SCHED_PERSISTENT) c.frame = 0;
     return c;
 }
 
@@ -267,13 +290,29 @@ int arith_mode(int mode, const KernelCfg &c)
     return mode == MODE_BF16 && c.products == 4 ? MODE_BF16X4 : mode;
 }
 
-void apply_cfg(clusco_handle h, int mode, const KernelCfg &c, Problem &p)
+// The set's share of configuration c: the reference frame (reference
+// candidates: the first models of the set `own`, whose chosen index lives
+// in its workspace slot) and the flag coefficients.
+void configure_set(const KernelCfg &c, const FlagCoefs &f, const ModelSet &own, ModelSet &s)
 {
-    const int am = arith_mode(mode, c);
-    p.x4 = am == MODE_BF16X4;
+    s.frame = c.frame;
+    s.ref_X = own.X;
+    s.ref_N = own.N;
+    s.ref_b = own.use_b;
+    s.refidx = own.refidx;
+    s.ref_own = &own == &s;
+    s.fw = f.fw;
+    s.fe = f.fe;
+}
+
+// The problem's share of configuration c.
+void configure_problem(const KernelCfg &c, int arith, const FlagCoefs &f, Problem &p)
+{
+    p.x4 = arith == MODE_BF16X4;
     p.band = c.band;
     p.cfg = c.id;
-    p.flag_coef = flag_coef(h, mode, p.L, am);
+    p.frame = c.frame;
+    p.flag_coef = f.on ? 1.0 : -1.0;
 }
 
 // A minimal JSON reader for the tuning file (objects, arrays, strings,
@@ -463,14 +502,17 @@ clusco_status parse_tuning(const std::string &text, const std::string &arch, Tun
             t.cfg.products = (int)pd->num;
             t.cfg.schedule = sc->str == "staged" ? SCHED_STAGED : sc->str == "persistent" ? SCHED_PERSISTENT : -1;
             t.cfg.band = (int)bd->num;
-            ok = t.mode >= 0 && nb->num == t.nb && lb->num == t.lb && t.nb >= 0 &&
+            const JVal *fr = e.get("frame");
+            if (fr) t.cfg.frame = fr->kind == JVal::NUM && (fr->num == 0 || fr->num == 1) ? (int)fr->num : -1;
+            ok = t.cfg.frame >= 0 && t.mode >= 0 && nb->num == t.nb && lb->num == t.lb && t.nb >= 0 &&
                  t.nb < (int)out.n_edges.size() && t.lb >= 0 && t.lb < (int)out.l_edges.size() &&
                  (t.cfg.products == 3 || t.cfg.products == 4) && t.cfg.schedule >= 0 &&
                  bd->num == t.cfg.band && t.cfg.band >= 1 && t.cfg.band <= 256;
         }
         if (!ok) {
             *err = "tuning file: bad entry (needs precision, n_bucket, l_bucket, products 3|4, "
-                   "schedule staged|persistent, band 1..256, buckets within the edges)";
+                   "schedule staged|persistent, band 1..256, optional frame 0|1, buckets "
+                   "within the edges)";
             return CLUSCO_ERR_INVALID_ARG;
         }
         out.entries.push_back(t);
@@ -541,6 +583,10 @@ ModelSet make_set(int mode, int64_t X, int64_t N, int64_t L, int64_t model0, int
     s.E = (int64_t)take(o, sizeof(double) * s.Np);
     s.cen = (int64_t)take(o, sizeof(double) * 3 * s.Np);
     s.E64 = (int64_t)take(o, sizeof(double) * s.Np);
+    s.U = (int64_t)take(o, sizeof(double) * 9 * s.Np);
+    s.PT = (int64_t)take(o, sizeof(double) * 9 * s.Np);
+    s.F = (int64_t)take(o, sizeof(double) * s.Np);
+    s.refidx = (int64_t)take(o, sizeof(int32_t));
     s.ops = (int64_t)take(o, op_bytes_per_model(mode, s.Lp) * s.Np);
     return s;
 }
@@ -564,6 +610,10 @@ Problem make_problem(const ModelSet &A, const ModelSet &B, int sym, double coef)
     p.cenB = B.cen;
     p.E64A = A.E64;
     p.E64B = B.E64;
+    p.UA = A.U;
+    p.PTB = B.PT;
+    p.FA = A.F;
+    p.FB = B.F;
     p.XA = A.X;
     p.XB = B.X;
     p.flag_coef = coef;
@@ -571,6 +621,7 @@ Problem make_problem(const ModelSet &A, const ModelSet &B, int sym, double coef)
     p.x4 = 0;
     p.band = KernelCfg{}.band;
     p.cfg = -1;
+    p.frame = A.frame;
     return p;
 }
 
@@ -582,25 +633,30 @@ struct SingleLayout {
     int emode;            // arithmetic of the contraction (x4 when chosen)
 };
 
-void configure(clusco_handle h, int mode, int64_t N, SingleLayout &s)
+// Configuration of a single problem of N models (frame: whether the
+// reference frame may be used; the backward never uses it).
+void configure(clusco_handle h, int mode, int64_t N, bool frame, SingleLayout &s)
 {
-    if (!h) {
-        s.emode = mode;
-        return;
-    }
-    s.cfg = config_for(h, mode, N, s.p.L);
-    apply_cfg(h, mode, s.cfg, s.p);
+    if (h) s.cfg = config_for(h, mode, N, s.A.L);
+    if (!frame) s.cfg.frame = 0;
     s.emode = arith_mode(mode, s.cfg);
+    const FlagCoefs f = flag_coefs(h, mode, s.emode, s.A.L);
+    // the reference is chosen among the first models of the first set, for
+    // both sets
+    configure_set(s.cfg, f, s.A, s.A);
+    configure_set(s.cfg, f, s.A, s.B);
 }
 
-SingleLayout single_layout(clusco_handle h, int mode, int64_t N, int64_t L)
+SingleLayout single_layout(clusco_handle h, int mode, int64_t N, int64_t L, bool frame = true)
 {
     SingleLayout s{};
     size_t o = 256;
     s.A = make_set(mode, 0, N, L, 0, 0, o);
     s.B = s.A;
+    configure(h, mode, N, frame, s);
+    s.B = s.A;
     s.p = make_problem(s.A, s.A, 1, -1.0);
-    configure(h, mode, N, s);
+    configure_problem(s.cfg, s.emode, flag_coefs(h, mode, s.emode, L), s.p);
     s.off_list = take(o, sizeof(FixEntry) * problem_wtiles(s.p));
     s.total = o;
     return s;
@@ -608,14 +664,16 @@ SingleLayout single_layout(clusco_handle h, int mode, int64_t N, int64_t L)
 
 // A cross comparison takes the configuration of the all-vs-all size with as
 // many pairs.
-SingleLayout cross_layout(clusco_handle h, int mode, int64_t Na, int64_t Nb, int64_t L)
+SingleLayout cross_layout(clusco_handle h, int mode, int64_t Na, int64_t Nb, int64_t L,
+                          bool frame = true)
 {
     SingleLayout s{};
     size_t o = 256;
     s.A = make_set(mode, 0, Na, L, 0, 0, o);
     s.B = make_set(mode, 0, Nb, L, s.A.Np, 1, o);
+    configure(h, mode, (int64_t)std::sqrt(2.0 * (double)Na * (double)Nb) + 1, frame, s);
     s.p = make_problem(s.A, s.B, 0, -1.0);
-    configure(h, mode, (int64_t)std::sqrt(2.0 * (double)Na * (double)Nb) + 1, s);
+    configure_problem(s.cfg, s.emode, flag_coefs(h, mode, s.emode, L), s.p);
     s.off_list = take(o, sizeof(FixEntry) * problem_wtiles(s.p));
     s.total = o;
     return s;
@@ -639,7 +697,8 @@ size_t grad_planes_bytes(int64_t n, int64_t L)
 BwdLayout bwd_layout(clusco_handle h, int mode, int64_t NA, int64_t NB, int64_t L, bool cross)
 {
     BwdLayout b{};
-    b.s = cross ? cross_layout(h, bwd_mode(mode), NA, NB, L) : single_layout(h, bwd_mode(mode), NA, L);
+    b.s = cross ? cross_layout(h, bwd_mode(mode), NA, NB, L, false)
+                : single_layout(h, bwd_mode(mode), NA, L, false);
     size_t o = b.s.total;
     const int64_t pairs = cross ? NA * NB : NA * (NA - 1) / 2;
     b.off_wq = take(o, sizeof(float) * 12 * (pairs > 0 ? pairs : 1));
@@ -769,7 +828,6 @@ clusco_status enqueue(clusco_handle h, int mode, const float *XA, const float *X
         fl.list = tl.list;
         coef = plan->first.flag_coef;
         tl.sched = plan->sched;
-        tl.mixed_x4 = plan->mixed_x4;
     }
     const int emode = single ? single->emode : plan->emode;
     if (timing) stage_mark(h, 0, s);
@@ -777,7 +835,24 @@ clusco_status enqueue(clusco_handle h, int mode, const float *XA, const float *X
     if (e != hipSuccess) return hip_fail(h, e, "prep launch");
     if (timing) stage_mark(h, 1, s);
     if (mode != MODE_FP64) {
-        e = launch_tile(emode, tl, s);
+        if (plan && plan->T4 > 0 && plan->T4 < plan->T) {
+            // a batch whose split-BF16 problems differ in their product
+            // count: the four-product tiles, then the three-product ones
+            TileLaunch t4 = tl;
+            t4.T = plan->T4;
+            t4.ctr = 1;
+            e = launch_tile(MODE_BF16X4, t4, s);
+            if (e == hipSuccess) {
+                TileLaunch t3 = tl;
+                t3.t0 = plan->T4;
+                t3.T = plan->T - plan->T4;
+                t3.ctr = 2;
+                e = launch_tile(MODE_BF16, t3, s);
+            }
+        } else {
+            tl.ctr = 1;
+            e = launch_tile(emode, tl, s);
+        }
         if (e != hipSuccess) return hip_fail(h, e, "tile launch");
     }
     if (timing) stage_mark(h, 2, s);
@@ -822,7 +897,8 @@ std::vector<int64_t> batch_key(clusco_handle h, int mode, const BatchInput &b, b
 // (padded length, then size) so the persistent kernel starts the longest
 // tiles first.  Returns the workspace size; fills tables when asked.
 struct PlanKernel {
-    int sched = SCHED_STAGED, emode = 0, mixed_x4 = 0;
+    int sched = SCHED_STAGED, emode = 0;
+    int64_t T4 = 0;
 };
 
 size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<ModelSet> *sets,
@@ -834,32 +910,48 @@ size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<M
     std::vector<Problem> P;
     int64_t model0 = 0;
     // each problem takes its bucket's configuration; the launch takes the
-    // schedule that most of the work (tiles x K-blocks x products) prefers
+    // schedule that most of the work (tiles x K-blocks x products) prefers,
+    // and under the persistent schedule no problem uses the reference frame
+    std::vector<KernelCfg> cfg(b.E);
     double vote[2] = {0.0, 0.0};
+    for (int32_t e = 0; e < b.E; ++e) {
+        if (b.N[e] < 2) continue;
+        cfg[e] = config_for(h, mode, b.N[e], b.L[e]);
+        const int64_t nb = round_up(b.N[e], TILE) / TILE;
+        vote[cfg[e].schedule == SCHED_PERSISTENT] += (double)tri_count(nb) *
+            (double)round_up(b.L[e], kblock(mode)) * (double)cfg[e].products;
+    }
+    const int sched = vote[1] > vote[0] ? SCHED_PERSISTENT : SCHED_STAGED;
     int nx4 = 0;
     for (int32_t e = 0; e < b.E; ++e) {
         if (b.N[e] < 2) continue;
         ModelSet s = make_set(mode, b.coff ? b.coff[e] : 0, b.N[e], b.L[e], model0, 0, o);
         model0 += s.Np;
+        KernelCfg c = cfg[e];
+        if (sched == SCHED_PERSISTENT) c.frame = 0;
+        const int am = arith_mode(mode, c);
+        const FlagCoefs f = flag_coefs(h, mode, am, b.L[e]);
+        configure_set(c, f, s, s);            // the reference is one of the ensemble's models
         S.push_back(s);
         Problem p = make_problem(s, s, 1, -1.0);
-        const KernelCfg c = config_for(h, mode, b.N[e], b.L[e]);
-        apply_cfg(h, mode, c, p);
+        configure_problem(c, am, f, p);
         p.out = b.ooff ? b.ooff[e] : 0;
         nx4 += p.x4;
-        vote[c.schedule == SCHED_PERSISTENT] +=
-            (double)problem_tiles(p) * (double)p.KB * (p.x4 ? 4.0 : 3.0);
         P.push_back(p);
     }
+    // four-product problems first (a launch of their own when mixed), then
+    // the most expensive tiles first
     std::stable_sort(P.begin(), P.end(), [](const Problem &x, const Problem &y) {
-        const int64_t cx = x.KB * (x.x4 ? 4 : 3), cy = y.KB * (y.x4 ? 4 : 3);
-        if (cx != cy) return cx > cy;
+        if (x.x4 != y.x4) return x.x4 > y.x4;
+        if (x.KB != y.KB) return x.KB > y.KB;
         return x.NA > y.NA;
     });
+    int64_t T4 = 0;
+    for (const Problem &p : P) T4 += p.x4 ? problem_tiles(p) : 0;
     if (pk) {
-        pk->sched = vote[1] > vote[0] ? SCHED_PERSISTENT : SCHED_STAGED;
+        pk->sched = sched;
         pk->emode = (nx4 > 0 && nx4 == (int)P.size()) ? MODE_BF16X4 : mode;
-        pk->mixed_x4 = nx4 > 0 && nx4 < (int)P.size();
+        pk->T4 = (nx4 > 0 && nx4 < (int)P.size()) ? T4 : 0;
     }
     int64_t t0 = 0, w0 = 0;
     for (Problem &p : P) {
@@ -912,7 +1004,7 @@ clusco_status create_plan(clusco_handle h, int mode, const BatchInput &b,
                              &p.total_models, &pk);
     p.sched = pk.sched;
     p.emode = pk.emode;
-    p.mixed_x4 = pk.mixed_x4;
+    p.T4 = pk.T4;
     p.nset = (int32_t)sets.size();
     p.nprob = (int32_t)probs.size();
     if (p.nprob > 0) {
@@ -1032,6 +1124,7 @@ clusco_status clusco_get_config(clusco_handle h, int64_t N, int64_t L, clusco_pr
     cfg->products = c.products;
     cfg->schedule = c.schedule;
     cfg->band = c.band;
+    cfg->frame = c.frame;
     cfg->source = c.source;
     cfg->bucket = c.id;
     return CLUSCO_OK;
@@ -1046,14 +1139,15 @@ clusco_status clusco_force_config(clusco_handle h, const clusco_config *cfg)
     } else {
         if ((cfg->products != 3 && cfg->products != 4) ||
             (cfg->schedule != CLUSCO_SCHED_STAGED && cfg->schedule != CLUSCO_SCHED_PERSISTENT) ||
-            cfg->band < 1 || cfg->band > 256)
+            cfg->band < 1 || cfg->band > 256 || (cfg->frame != 0 && cfg->frame != 1))
             return fail(h, CLUSCO_ERR_INVALID_ARG,
-                        "need products 3 or 4, a known schedule and band in 1..256");
+                        "need products 3 or 4, a known schedule, band in 1..256, frame 0 or 1");
         h->forced = true;
         h->force = KernelCfg{};
         h->force.products = cfg->products;
         h->force.schedule = cfg->schedule;
         h->force.band = cfg->band;
+        h->force.frame = cfg->frame;
     }
     ++h->tune_gen;
     return CLUSCO_OK;

@@ -162,18 +162,18 @@ __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const
                 step[p] = eq2_newton(l[p], c2[p], c1[p], c0[p]);
         }
     }
-    // The hardware reciprocal square roots (relative error below 6e-8,
-    // measured on gfx950) are used unrefined here: the score tolerance only
-    // needs the sum to ~1e-6 relative, and the fix-up flag budgets this error
-    // in the precision's epsilon (pairs that need more go to the FP64 fix-up,
-    // which refines).
+    // The hardware reciprocal square roots (relative error below 6e-8 on
+    // gfx950) get one Newton step each: an error of that size in the sum
+    // s1 + s2 + S s3, whose magnitude is the radii E, would dominate the
+    // contraction error of the reference frame (proportional to the residual
+    // radii only).
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const double l1 = fmax(l[p], fmax(c2[p] * (1.0 / 3.0), 1e-300));
-        const double r1 = __builtin_amdgcn_rsq(l1);
+        const double r1 = rsqrt_refined(l1);
         const double t = fma(2.0 * det[p], r1, c2[p] - l1);        // (s2 + S s3)^2
         const double tp = fmax(t, 1e-300);
-        const double sum = fma(l1, r1, tp * __builtin_amdgcn_rsq(tp));   // s1 + s2 + S s3
+        const double sum = fma(l1, r1, tp * rsqrt_refined(tp));   // s1 + s2 + S s3
         out[p] = fma(-2.0, sum, ea[p] + eb[p]);
     }
 }

@@ -1,9 +1,11 @@
 // FP64 fix-up.  Pairs whose contraction error could exceed the tolerance are
-// those with a small score relative to the models' radii: Eq. 2 subtracts
-// 2(s1 + s2 + S s3) from R_A^2 + R_B^2, so an absolute error d in the
-// correlation becomes an error of about d (E_A + E_B) / (L cRMSD) in cRMSD.
-// The tile kernel lists every 32x32 block holding a pair whose stored score is
-// below flag_coef (E_i + E_j); this kernel re-evaluates that test on the
+// those with a small score relative to the size of what was contracted: Eq. 2
+// subtracts 2(s1 + s2 + S s3) from R_A^2 + R_B^2, so an absolute error d in
+// the correlation becomes an error of about d / (L cRMSD) in cRMSD, and d
+// grows with the squared size of the contracted vectors (the models, or their
+// residuals from the reference frame).  Prep folds that into one flag weight
+// F per model; the tile kernel lists every 32x32 block holding a pair whose
+// stored score is below F_i + F_j, and this kernel re-evaluates that test on the
 // stored scores of each listed block, compacts the flagged pairs in LDS and
 // recomputes each one from the raw float32 coordinates entirely in FP64
 // (see pair_corr_span and pair_score), then the same Eq. 2 epilogue.  With
@@ -138,8 +140,8 @@ __global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
         const uint32_t b = a.list[t].blk;
         const int64_t Ra = b >> 16, Rb = b & 0xFFFFu;
         const int64_t NA = p.NA, NB = p.NB, L = p.L;
-        const double *EA = (const double *)(a.ws + p.EA);
-        const double *EB = (const double *)(a.ws + p.EB);
+        const double *FA = (const double *)(a.ws + p.FA);
+        const double *FB = (const double *)(a.ws + p.FB);
         float *out = a.out + p.out;
         if (tid == 0) cnt = 0;
         __syncthreads();
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
                     need = (a.emit.masks[32 * t + (q >> 5)] >> (q & 31)) & 1u;
                 } else {
                     const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
-                    need = (double)out[k] < p.flag_coef * (EA[i] + EB[j]);
+                    need = (double)out[k] < FA[i] + FB[j];
                 }
                 if (need) todo[atomicAdd(&cnt, 1)] = (uint16_t)q;
             }
@@ -260,8 +262,8 @@ __global__ __launch_bounds__(FIX_DTHREADS, FIX_DWAVES) void fixup_dense_kernel(F
             Rb = b & 0xFFFFu;
         }
         const int64_t NA = p.NA, NB = p.NB, L = p.L;
-        const double *EA = (const double *)(a.ws + p.EA);
-        const double *EB = (const double *)(a.ws + p.EB);
+        const double *FA = (const double *)(a.ws + p.FA);
+        const double *FB = (const double *)(a.ws + p.FB);
         float *out = a.out + p.out;
         // which kernel takes a listed block: every block in `all` mode; in
         // threshold mode the count of candidates in the ownership mask; else
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(FIX_DTHREADS, FIX_DWAVES) void fixup_dense_kernel(F
                 const bool live = p.sym ? (i < j && j < NA) : (i < NA && j < NB);
                 if (live) {
                     const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
-                    c = (double)out[k] < p.flag_coef * (EA[i] + EB[j]) ? FIX_SAMPLE : 0;
+                    c = (double)out[k] < FA[i] + FB[j] ? FIX_SAMPLE : 0;
                 }
             }
             if (c) atomicAdd(&cnt, c);
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(FIX_DTHREADS, FIX_DWAVES) void fixup_dense_kernel(F
                     need = (a.emit.masks[32 * t + (q >> 5)] >> (q & 31)) & 1u;
                 } else {
                     const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
-                    need = (double)out[k] < p.flag_coef * (EA[i] + EB[j]);
+                    need = (double)out[k] < FA[i] + FB[j];
                 }
                 if (need) todo[atomicAdd(&cnt, 1)] = (uint16_t)q;
             }

@@ -130,6 +130,21 @@ __host__ inline size_t op_bytes_per_model(int mode, int64_t Lp)
 // relative to the bases passed at launch (coordinate arrays, workspace,
 // output), so a table of sets or problems does not depend on the buffers.
 
+// Reference frame.  With `frame` set, every model a of a set is first
+// superimposed onto a reference structure r (a centred model of the
+// problem's first set: of its first REF_CANDIDATES models the one with the
+// smallest sum of squared cRMSD to the others, so that an outlier is not
+// picked) by its optimal rotation R_a, and the contraction runs
+// on the residuals d = R_a a - r instead of the coordinates.  For two models
+// the correlation of the superimposed models is
+//     H' = sum (r + d_A)(r + d_B)^T = G + P_A + P_B^T + D_AB,
+//     G = sum r r^T,  P = sum d r^T,  D_AB = sum d_A d_B^T,
+// and H' = R_A H R_B^T has the singular values and determinant sign of H, so
+// Eq. 2 is unchanged.  Only D_AB (residuals of the size of the models'
+// deviation from r, not of their radius of gyration) goes through the
+// low-precision MFMA product; U = G + P and P^T are per-model FP64 terms the
+// epilogue adds back.  Without `frame`, R = I and r = 0: U = P^T = 0 and
+// d = a (the plain contraction).
 struct ModelSet {
     int64_t X;            // float offset of the set's first coordinate
     int64_t N, Np, L, Lp, KB;
@@ -138,9 +153,20 @@ struct ModelSet {
     int64_t E;            // byte offset of the radii (double [Np])
     int64_t cen;          // byte offset of the centroids (double [Np][3])
     int64_t E64;          // byte offset of the exact FP64 radii of the raw coordinates
+    int64_t U;            // byte offset of U = G + P (double [Np][9], row-major)
+    int64_t PT;           // byte offset of P^T (double [Np][9])
+    int64_t F;            // byte offset of the flag weights (double [Np], see Problem)
+    int64_t ref_X;        // float offset of the reference candidates (models of L atoms)
+    int64_t ref_N;        // models the candidates are taken from
+    int64_t refidx;       // byte offset of the chosen candidate's index (int32)
+    double fw, fe;        // flag weight F = fw W + fe E, W = sum |d|^2
     int32_t use_b;        // coordinates come from the second base pointer
-    int32_t pad;
+    int32_t ref_b;        // the reference candidates come from the second base pointer
+    int32_t frame;        // residuals from the reference frame (else R = I, r = 0)
+    int32_t ref_own;      // this set's launch chooses the reference (else it shares one)
 };
+
+constexpr int REF_CANDIDATES = 8;
 
 struct Problem {
     int64_t NA, NB, L, KB;
@@ -150,14 +176,18 @@ struct Problem {
     int64_t wtile0;       // first 32x32 block of this problem in the launch
     int64_t opsA, opsB, EA, EB, cenA, cenB;   // workspace byte offsets
     int64_t E64A, E64B;   // exact FP64 radii (fix-up)
+    int64_t UA, PTB;      // reference-frame terms: U of the rows, P^T of the columns
+    int64_t FA, FB;       // flag weights: a pair is recomputed when score < F_i + F_j
     int64_t XA, XB;       // float offsets into the first / second coordinate base
     int64_t out;          // float offset into the output base
-    double flag_coef;     // flag a pair when score < flag_coef (E_i + E_j); <= 0 never
+    double flag_coef;     // > 0: the FP64 fix-up runs (flag weights in FA, FB); <= 0 never
     int32_t sym;          // 1: all-vs-all (packed, i < j); 0: dense NA x NB
     // kernel configuration chosen for this problem's (N, L) bucket
     int32_t x4;           // split-BF16: the fourth product lo*lo' is issued too
     int32_t band;         // tile rows per band of the tile order
     int32_t cfg;          // bucket of the tuning table the choice came from (-1: default)
+    int32_t frame;        // the sets use the reference frame (epilogue adds U, P^T)
+    int32_t pad2;
 };
 
 // Tile schedules (a tuning choice per problem bucket).
@@ -192,7 +222,7 @@ struct PrepLaunch {
     int32_t nset;
     int32_t mode;
     int64_t total;        // padded models over all sets
-    int *counters;        // [0] fix-up list length, [1] work counter (zeroed here)
+    int *counters;        // [0] fix-up list length, [1], [2] work counters (zeroed here)
     unsigned long long *zero64;   // zeroed here too when not null (emission count)
 };
 
@@ -219,7 +249,8 @@ struct TileLaunch {
     int32_t kind;         // TK_SYM, TK_RECT, TK_BATCH
     int64_t T;            // 64x64 tiles in the launch
     int32_t sched;        // SCHED_STAGED or SCHED_PERSISTENT (forward only)
-    int32_t mixed_x4;     // TK_BATCH split-BF16: problems differ in x4
+    int32_t ctr;          // TK_BATCH persistent: index of its work counter in counters
+    int64_t t0;           // TK_BATCH: first tile of this launch (tiles t0 .. t0 + T - 1)
     int *counters;
     FixEntry *list;
     // backward pass only: forward scores, incoming gradients, and the per-pair
@@ -344,7 +375,7 @@ struct WsLayout {
     int64_t max_blocks;
 };
 
-hipError_t launch_prep(const PrepLaunch &a, hipStream_t s);
+hipError_t launch_prep(const PrepLaunch &a, hipStream_t s);   // also chooses the references
 hipError_t launch_tile(int mode, const TileLaunch &a, hipStream_t s, int op = OP_FWD);
 hipError_t launch_grad(const GradLaunch &a, hipStream_t s);
 hipError_t launch_grad_planes(const float *X, const double *cen, float *P, int64_t N, int64_t L,

@@ -49,23 +49,12 @@ __device__ __forceinline__ f32x16 mfma_split(u32x4 a, u32x4 b, f32x16 c)
                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
-// Whether the split-BF16 contraction of problem p issues the fourth product
-// lo*lo': always in the x4 mode; in a batch of split-BF16 problems per
-// problem (the tuning table chooses three or four products per bucket).
-template <int MODE, int KIND>
-__device__ __forceinline__ bool issue_lolo(const TileLaunch &a, const Problem &p)
-{
-    if constexpr (MODE == MODE_BF16X4) return true;
-    else if constexpr (MODE == MODE_BF16 && KIND == TK_BATCH) return a.mixed_x4 && p.x4;
-    else return false;
-}
-
 // Contraction of one 32x32 wave tile: acc[3c+d] += X_c[Ra rows] X_d[Rb rows]^T
 template <int MODE>
 __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int64_t Ra,
-                                         int64_t Rb, int64_t KB, int lane, bool lolo,
-                                         f32x16 acc[9])
+                                         int64_t Rb, int64_t KB, int lane, f32x16 acc[9])
 {
+    constexpr bool lolo = MODE == MODE_BF16X4;   // the fourth product lo*lo'
     if constexpr (MODE == MODE_FP32) {
         const f32x4 *pa = (const f32x4 *)opsA + Ra * KB * 3 * 64 + lane;
         const f32x4 *pb = (const f32x4 *)opsB + Rb * KB * 3 * 64 + lane;
@@ -138,7 +127,7 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
                     acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
-            if (lolo) {
+            if constexpr (lolo) {
                 // fourth product lo*lo': the split then carries no dropped term
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -202,8 +191,9 @@ __device__ __forceinline__ WaveJob decode_job(const TileLaunch &a, int64_t t, in
     int64_t bi, bj;
     int32_t e = 0;
     if constexpr (KIND == TK_BATCH) {
-        e = table_find(a.table, a.nprob, t, [](const Problem &q) { return q.tile0; });
-        band_decode(t - a.table[e].tile0, a.table[e].nbA, a.table[e].band, &bi, &bj);
+        const int64_t tg = a.t0 + t;
+        e = table_find(a.table, a.nprob, tg, [](const Problem &q) { return q.tile0; });
+        band_decode(tg - a.table[e].tile0, a.table[e].nbA, a.table[e].band, &bi, &bj);
     } else if constexpr (KIND == TK_SYM) {
         band_decode(t, a.prob.nbA, a.prob.band, &bi, &bj);
     } else {
@@ -219,12 +209,13 @@ __device__ __forceinline__ WaveJob decode_job(const TileLaunch &a, int64_t t, in
     return job;
 }
 
-// The radii a wave's epilogue needs, loaded once (not once per pair, which
-// would put a dependent memory round trip in front of every pair): E of the
-// lane's column j = Rb*32 + lane%32, and E of row Ra*32 + lane%32, from which
-// each pair takes its row's radius with a cross-lane shuffle.
+// The per-model values a wave's epilogue needs, loaded once (not once per
+// pair, which would put a dependent memory round trip in front of every
+// pair): the radius E and the flag weight F of the lane's column
+// j = Rb*32 + lane%32, and of row Ra*32 + lane%32, from which each pair takes
+// its row's values with a cross-lane shuffle.
 struct EpiRadii {
-    double ej, erow;
+    double ej, erow, fj, frow;
 };
 
 __device__ __forceinline__ EpiRadii epi_radii(const TileLaunch &a, const Problem &p,
@@ -232,7 +223,10 @@ __device__ __forceinline__ EpiRadii epi_radii(const TileLaunch &a, const Problem
 {
     const double *EA = (const double *)(a.ws + p.EA);
     const double *EB = (const double *)(a.ws + p.EB);
-    return EpiRadii{EB[job.Rb * ROWBLK + (lane & 31)], EA[job.Ra * ROWBLK + (lane & 31)]};
+    const double *FA = (const double *)(a.ws + p.FA);
+    const double *FB = (const double *)(a.ws + p.FB);
+    const int64_t j = job.Rb * ROWBLK + (lane & 31), i = job.Ra * ROWBLK + (lane & 31);
+    return EpiRadii{EB[j], EA[i], FB[j], FA[i]};
 }
 
 // E of row Ra*32 + r (r < 32) from the lane that loaded it.
@@ -241,22 +235,53 @@ __device__ __forceinline__ double row_radius(const EpiRadii &er, int r)
     return __shfl(er.erow, r, 64);
 }
 
+// F of row Ra*32 + r.
+__device__ __forceinline__ double row_flag(const EpiRadii &er, int r)
+{
+    return __shfl(er.frow, r, 64);
+}
+
+// Correlation of the pair in accumulator slot r, in FP64: the contraction's
+// value, plus in the reference frame U of the row (urow: its 9 values) and
+// P^T of the column (pcol: its 9 values), in that order in every kernel.
+template <bool FRAME>
+__device__ __forceinline__ void pair_h(const f32x16 acc[9], int r, const double *urow,
+                                       const double *pcol, double h[9])
+{
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+        h[u] = (double)acc[u][r];
+        if constexpr (FRAME) h[u] = (h[u] + urow[u]) + pcol[u];
+    }
+}
+
+// Where the epilogue finds the reference-frame terms of its wave's block: U
+// of its 32 rows and P^T of its 32 columns, 9 doubles per model (in LDS for
+// the staged kernel, in the workspace for the persistent one).
+struct FrameTerms {
+    const double *urow, *pcol;
+};
+
 // FP64 Eq. 2 epilogue and store of one wave's 32x32 block.  The lane holds
 // column j = lane%32 and rows 8(r/4) + 4(lane/32) + r%4 of accumulator slot r.
 // Every slot is evaluated (padding rows and columns have H = 0 and E = 0,
 // which is finite); only the store and the flag are predicated, so the FP64
-// work runs without divergent branches.
-__device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
-                                         const WaveJob &job, int lane, const f32x16 acc[9],
-                                         const EpiRadii &er)
+// work runs without divergent branches.  urow: the U values of the wave's 32
+// rows (reference frame).  A pair is listed for the FP64 fix-up when its
+// score is below F_i + F_j and the problem runs the fix-up.
+template <bool FRAME>
+__device__ __forceinline__ void epilogue_t(const TileLaunch &a, const Problem &p,
+                                           const WaveJob &job, int lane, const f32x16 acc[9],
+                                           const EpiRadii &er, const FrameTerms &ft)
 {
     const int64_t NA = p.NA, NB = p.NB;
     float *out = a.out + p.out;
     const double invL = 1.0 / (double)p.L;
-    const double coef = p.flag_coef;
+    const bool fix = p.flag_coef > 0.0;
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
-    const double Ej = er.ej;
+    const double Ej = er.ej, Fj = er.fj;
     const bool jlive = j < (p.sym ? NA : NB);
+    const double *pcol = ft.pcol + 9 * (lane & 31);
     bool flagged = false;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -268,9 +293,9 @@ __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
             double h[EPI_NP][9], ei[EPI_NP], ej[EPI_NP], lr2[EPI_NP];
 #pragma unroll
             for (int b = 0; b < EPI_NP; ++b) {
-#pragma unroll
-                for (int u = 0; u < 9; ++u) h[b][u] = (double)acc[u][4 * g + q0 + b];
-                ei[b] = row_radius(er, 8 * g + 4 * (lane >> 5) + q0 + b);
+                const int rr = 8 * g + 4 * (lane >> 5) + q0 + b;
+                pair_h<FRAME>(acc, 4 * g + q0 + b, ft.urow + 9 * rr, pcol, h[b]);
+                ei[b] = row_radius(er, rr);
                 ej[b] = Ej;
             }
             eq2_lrmsd2_batch<EPI_NP, EPI_STEPS>(h, ei, ej, lr2);
@@ -282,7 +307,8 @@ __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
                 const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[b] * invL, 0.0));
                 const bool live = jlive && (p.sym ? i < j : i < NA);
                 if (live) out[base + j] = v;
-                flagged |= live && (double)v < coef * (ei[b] + Ej);
+                const double fi = row_flag(er, 8 * g + 4 * (lane >> 5) + q0 + b);
+                flagged |= fix && live && (double)v < fi + Fj;
                 base += p.sym ? NA - i - 2 : NB;
             }
         }
@@ -291,6 +317,14 @@ __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
         const int s = atomicAdd(&a.counters[0], 1);
         a.list[s] = FixEntry{(uint32_t)job.pidx, ((uint32_t)job.Ra << 16) | (uint32_t)job.Rb};
     }
+}
+
+__device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
+                                         const WaveJob &job, int lane, const f32x16 acc[9],
+                                         const EpiRadii &er, const FrameTerms &ft)
+{
+    if (p.frame) epilogue_t<true>(a, p, job, lane, acc, er, ft);
+    else epilogue_t<false>(a, p, job, lane, acc, er, ft);
 }
 
 // Backward epilogue: per live pair, w = g / (L cRMSD) (0 where the score
@@ -358,31 +392,34 @@ struct ThrPairs {
     uint32_t total;   // pairs of the wave to emit
 };
 
-__device__ __forceinline__ void thr_scores(const TileLaunch &a, const Problem &p, const WaveJob &job,
-                                           int lane, const f32x16 acc[9], const EpiRadii &er,
-                                           ThrPairs &tp)
+template <bool FRAME>
+__device__ __forceinline__ void thr_scores_t(const TileLaunch &a, const Problem &p,
+                                             const WaveJob &job, int lane, const f32x16 acc[9],
+                                             const EpiRadii &er, const FrameTerms &ft,
+                                             ThrPairs &tp)
 {
     const int64_t NA = p.NA;
     const double invL = 1.0 / (double)p.L;
-    const double coef = p.flag_coef;
+    const bool fix = p.flag_coef > 0.0;
     const float cutoff = (float)a.emit.cutoff;
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
-    const double Ej = er.ej;
+    const double Ej = er.ej, Fj = er.fj;
     const bool jlive = j < NA;
+    const double *pcol = ft.pcol + 9 * (lane & 31);
     uint32_t emit = 0, flag = 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t i = job.Ra * ROWBLK + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int rr = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         double h[1][9], ei[1], ej[1], lr2[1];
-#pragma unroll
-        for (int u = 0; u < 9; ++u) h[0][u] = (double)acc[u][r];
-        const double Ei = row_radius(er, 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
+        pair_h<FRAME>(acc, r, ft.urow + 9 * rr, pcol, h[0]);
+        const double Ei = row_radius(er, rr);
         ei[0] = Ei;
         ej[0] = Ej;
         eq2_lrmsd2_batch<1, EPI_STEPS>(h, ei, ej, lr2);   // the forward's arithmetic
         const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[0] * invL, 0.0));
         const bool live = jlive && i < j;
-        const bool fl = live && (double)v < coef * (Ei + Ej);
+        const bool fl = fix && live && (double)v < row_flag(er, rr) + Fj;
         tp.vs[r] = v;
         flag |= (uint32_t)fl << r;
         emit |= (uint32_t)(live && !fl && v < cutoff) << r;
@@ -411,6 +448,14 @@ __device__ __forceinline__ void thr_scores(const TileLaunch &a, const Problem &p
     tp.total = total;
 }
 
+__device__ __forceinline__ void thr_scores(const TileLaunch &a, const Problem &p, const WaveJob &job,
+                                           int lane, const f32x16 acc[9], const EpiRadii &er,
+                                           const FrameTerms &ft, ThrPairs &tp)
+{
+    if (p.frame) thr_scores_t<true>(a, p, job, lane, acc, er, ft, tp);
+    else thr_scores_t<false>(a, p, job, lane, acc, er, ft, tp);
+}
+
 __device__ __forceinline__ void thr_write(const TileLaunch &a, const WaveJob &job, int lane,
                                           const ThrPairs &tp, unsigned long long base)
 {
@@ -434,10 +479,10 @@ __device__ __forceinline__ void thr_write(const TileLaunch &a, const WaveJob &jo
 // One wave's block on its own: one atomic per wave.
 __device__ __forceinline__ void thr_epilogue(const TileLaunch &a, const Problem &p,
                                              const WaveJob &job, int lane, const f32x16 acc[9],
-                                             const EpiRadii &er)
+                                             const EpiRadii &er, const FrameTerms &ft)
 {
     ThrPairs tp;
-    thr_scores(a, p, job, lane, acc, er, tp);
+    thr_scores_t<false>(a, p, job, lane, acc, er, ft, tp);
     if (tp.total == 0) return;
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(a.emit.count, (unsigned long long)tp.total);
@@ -481,7 +526,7 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
         if (threadIdx.x == 0) {
             int64_t t;
             if constexpr (KIND == TK_BATCH) {
-                t = atomicAdd(&a.counters[1], 1);
+                t = atomicAdd(&a.counters[a.ctr], 1);
             } else {
                 t = c0 + jw + per * ph;
                 if (t >= c1) t = a.T;
@@ -500,15 +545,17 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
                 const Problem &p = problem_of<KIND>(a, job.pidx);
-                contract<MODE>(a.ws + p.opsA, a.ws + p.opsB, job.Ra, job.Rb, p.KB, lane,
-                               issue_lolo<MODE, KIND>(a, p), acc);
+                contract<MODE>(a.ws + p.opsA, a.ws + p.opsB, job.Ra, job.Rb, p.KB, lane, acc);
             }
         } else if (job.active) {
+            // the persistent schedule serves problems without the reference
+            // frame only (the host never pairs the two)
             const Problem &pe = problem_of<KIND>(a, job.pidx);
             const EpiRadii er = epi_radii(a, pe, job, lane);
-            if constexpr (OP == OP_FWD) epilogue(a, pe, job, lane, acc, er);
+            const FrameTerms ft{nullptr, nullptr};
+            if constexpr (OP == OP_FWD) epilogue_t<false>(a, pe, job, lane, acc, er, ft);
             else if constexpr (OP == OP_BWD) bwd_epilogue(a, pe, job, lane, acc, er);
-            else thr_epilogue(a, pe, job, lane, acc, er);
+            else thr_epilogue(a, pe, job, lane, acc, er, ft);
             job.active = 0;
         }
     }
@@ -540,25 +587,36 @@ struct StageGeom {
 // (global_load_lds_dwordx4, no registers): load m of wave w moves 64
 // consecutive chunks, lane l's 16 bytes landing at slot + 256 m + 64 w + l.
 // The wave's 64 chunks always lie in one region (REGION is a multiple of 64).
-// kb < 0 issues the same number of loads from the first chunks of A (always
-// present, cached), so that every step has the same count in flight; the
-// slot they fill is not read again.
+// kb < 0 issues the same number of loads, so that every step has the same
+// count in flight: with kb = STAGE_FRAME, into chunks 0 .. 2 FRAME_CHUNKS - 1,
+// the reference-frame terms of the tile (U of its 64 rows, then P^T of its 64
+// columns, 9 doubles per model, contiguous in the workspace), the rest from
+// the first chunks of A (always present, cached) like every other kb < 0;
+// nothing reads a slot filled with the latter again.
+constexpr int64_t STAGE_PAST = -1, STAGE_FRAME = -2;
+constexpr int FRAME_CHUNKS = 2 * ROWBLK * 9 * 8 / 16;   // 16-byte chunks per 64 models
+
 template <int MODE>
 __device__ __forceinline__ void stage_dma(const Problem &p, const char *ws, int64_t rA,
                                           int64_t rB, int64_t kb, int tid, int w, u32x4 *slot)
 {
     using G = StageGeom<MODE>;
+    static_assert(2 * FRAME_CHUNKS <= G::SLOT, "frame terms fit a slot");
     const int64_t KB = p.KB;
     const bool live = kb >= 0;
     const u32x4 *ops = (const u32x4 *)(ws + p.opsA);
     const u32x4 *rowA = ops + (rA * KB + (live ? kb : 0)) * G::REGION;
     const u32x4 *rowB = (const u32x4 *)(ws + p.opsB) + (rB * KB + (live ? kb : 0)) * G::REGION;
     const int64_t next = KB * G::REGION;            // the next row block, same K-block
+    const u32x4 *fU = (const u32x4 *)(ws + p.UA) + rA * (ROWBLK * 9 * 8 / 16);
+    const u32x4 *fP = (const u32x4 *)(ws + p.PTB) + rB * (ROWBLK * 9 * 8 / 16);
 #pragma unroll
     for (int m = 0; m < G::PER; ++m) {
         const int q = tid + 256 * m;
         const int region = q / G::REGION, off = q % G::REGION;
         const u32x4 *src = live ? (region < 2 ? rowA : rowB) + (region & 1) * next + off : ops + off;
+        if (kb == STAGE_FRAME && q < 2 * FRAME_CHUNKS)
+            src = q < FRAME_CHUNKS ? fU + q : fP + (q - FRAME_CHUNKS);
         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
                                          (void __attribute__((address_space(3))) *)(slot + 256 * m + 64 * w),
                                          16, 0, 0);
@@ -598,6 +656,7 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
         t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     }
     if (t >= a.T) return;                          // uniform over the workgroup
+    if constexpr (KIND == TK_BATCH) t += a.t0;
     int32_t e = 0;
     if constexpr (KIND == TK_BATCH)
         e = table_find(a.table, a.nprob, t, [](const Problem &q) { return q.tile0; });
@@ -606,7 +665,7 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     if constexpr (KIND == TK_RECT) band_decode_rect(t, p.nbA, p.nbB, p.band, &bi, &bj);
     else band_decode(t - p.tile0, p.nbA, p.band, &bi, &bj);
     const int64_t KB = p.KB;
-    const bool lolo = issue_lolo<MODE, KIND>(a, p);
+    constexpr bool lolo = MODE == MODE_BF16X4;     // the fourth product lo*lo'
 
     WaveJob job;
     job.Ra = 2 * bi + wy;
@@ -616,12 +675,18 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
                  job.Rb * ROWBLK < p.NB;
     // the epilogue's radii, loaded with the first K-blocks
     const EpiRadii er = epi_radii(a, p, job, lane);
+    // In the reference frame the tile's frame terms travel like an operand
+    // K-block, into the slot of K-block KB (the first step past the end, or
+    // the prologue when KB = 1), which no step reads; they have landed once
+    // the last step's wait and barrier have passed.
+    const bool fterms = OP != OP_BWD && p.frame;
+    const int64_t kb_frame = fterms ? STAGE_FRAME : STAGE_PAST;
     // the contraction runs at a raised wave priority: a SIMD's other wave is
     // usually in its FP64 epilogue, and the MFMA issue should not wait behind
     // that stream of VALU instructions
     __builtin_amdgcn_s_setprio(3);
     stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 0, tid, w, slot0);
-    if (KB > 1) stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 1, tid, w, slot1);
+    stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, KB > 1 ? 1 : kb_frame, tid, w, slot1);
     wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
 
@@ -637,7 +702,8 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     // The barrier needs no memory fence: each wave's own waits order its
     // loads, and the LDS reads are complete once their MFMAs have issued.
     auto step = [&](int64_t kb, const u32x4 *cur, u32x4 *nxt) {
-        stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, kb + 2 < KB ? kb + 2 : -1, tid, w, nxt);
+        stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj,
+                        kb + 2 < KB ? kb + 2 : (kb + 2 == KB ? kb_frame : STAGE_PAST), tid, w, nxt);
         pin_order();
         const u32x4 *sA = cur + wy * G::REGION + lane;
         const u32x4 *sB = cur + (2 + wx) * G::REGION + lane;
@@ -687,7 +753,7 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
                     acc[3 * c + d] = mfma_split<MODE>(Ah[c], Bl[d], acc[3 * c + d]);
-            if (lolo) {
+            if constexpr (lolo) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -718,6 +784,9 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     if (kb + 1 < KB) step(kb + 1, slot1, slot0);
     wait_vmcnt<0>();    // no load into LDS outlives the workgroup
     __builtin_amdgcn_s_setprio(0);
+    const int fs = (int)(KB % 3);
+    const double *fbase = (const double *)(fs == 0 ? slot0 : fs == 1 ? slot1 : slot2);
+    const FrameTerms ft{fbase + 9 * ROWBLK * wy, fbase + 9 * ROWBLK * (2 + wx)};
 
     if constexpr (OP == OP_THR) {
         // the four waves' emission counts go to the output counter in one
@@ -726,7 +795,7 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
         __shared__ unsigned long long wbase;
         ThrPairs tp;
         tp.total = 0;
-        if (job.active) thr_scores(a, p, job, lane, acc, er, tp);
+        if (job.active) thr_scores(a, p, job, lane, acc, er, ft, tp);
         if (lane == 0) wtot[w] = tp.total;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -741,7 +810,7 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
         }
     } else if (job.active) {
         if constexpr (OP == OP_BWD) bwd_epilogue(a, p, job, lane, acc, er);
-        else epilogue(a, p, job, lane, acc, er);
+        else epilogue(a, p, job, lane, acc, er, ft);
     }
 }
 

@@ -15,6 +15,9 @@ clusco_force_config, and records the fastest:
              persistent (ping-pong workgroups)
   band       tile rows per band of the tile order (only where the tile grid
              is wider than a band)
+  frame      contract the models (0) or their residuals from the reference
+             structure after superposition onto it (1; far fewer pairs for
+             the fix-up, a few more FP64 operations per pair)
 
 Times are HIP events on the stream the library launches on (torch's current
 stream).  The table is loaded by the library at handle creation
@@ -84,7 +87,9 @@ def candidates(prec, N):
     nb = -(-N // 64)
     bands = [8, 16, 32] if nb > 16 else [16]
     prods = {"split_bf16": [3, 4], "split_bf16x4": [4]}.get(prec, [3])
-    return [(p, sch, b) for p in prods for sch in ("staged", "persistent") for b in bands]
+    # the persistent schedule serves problems without the reference frame
+    return [(p, sch, b, f) for p in prods for sch in ("staged", "persistent") for b in bands
+            for f in ((0, 1) if sch == "staged" else (0,))]
 
 
 def main(argv=None):
@@ -123,19 +128,19 @@ def main(argv=None):
                 ws = torch.empty(max(256, binding.workspace_size(N, L, p)), dtype=torch.uint8,
                                  device=dev)
                 ms = {}
-                for prod, sch, band in candidates(prec, N):
-                    binding.force_config(prod, sch, band)
-                    ms[f"x{prod}/{sch}/{band}"] = time_call(
+                for prod, sch, band, fr in candidates(prec, N):
+                    binding.force_config(prod, sch, band, fr)
+                    ms[f"x{prod}/{sch}/{band}/f{fr}"] = time_call(
                         torch, lambda: binding.crmsd_matrix(x, p, out=out, ws=ws))
                 binding.force_config(None)
-                default = "x4/staged/16" if prec == "split_bf16x4" else "x3/staged/16"
+                default = ("x4" if prec == "split_bf16x4" else "x3") + "/staged/16/f1"
                 best = min(ms, key=ms.get)
                 if default in ms and ms[default] <= ms[best] * (1.0 + args.margin):
                     best = default
-                prod, sch, band = best.split("/")
+                prod, sch, band, fr = best.split("/")
                 entries.append({"precision": prec, "n_bucket": nb, "l_bucket": lb,
                                 "N": N, "L": L, "products": int(prod[1:]), "schedule": sch,
-                                "band": int(band), "ms": ms,
+                                "band": int(band), "frame": int(fr[1:]), "ms": ms,
                                 "pairs_per_s": P / (ms[best] * 1e-3)})
                 log(f"[tune] {prec:13s} N={N:6d} L={L:4d}: {best:22s} {ms[best]:8.3f} ms "
                     f"(default {ms.get(default, float('nan')):8.3f} ms)")

@@ -1,6 +1,6 @@
 """GPU parity of every kernel configuration the tuning table can choose
-(products 3 / 4 for split-BF16, staged / persistent schedule, band widths)
-against the FP64 oracle, for single ensembles, cross comparisons and
+(products 3 / 4 for split-BF16, staged / persistent schedule, band widths,
+reference frame on / off) against the FP64 oracle, for single ensembles, cross comparisons and
 batches; a batch whose ensembles take different configurations (mixed
 product counts) must equal single calls made under the same table."""
 import json
@@ -15,7 +15,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "bf16x4": 5e-4}
-CONFIGS = [(p, s, b) for p in (3, 4) for s in ("staged", "persistent") for b in (8, 16, 3)]
+CONFIGS = [(p, s, b, f) for p in (3, 4) for s in ("staged", "persistent") for b in (8, 16, 3)
+           for f in (0, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -45,13 +46,13 @@ def ens_1100():
     return x, oracle.crmsd_matrix(x)
 
 
-@pytest.mark.parametrize("cfg", CONFIGS, ids=[f"x{p}-{s}-b{b}" for p, s, b in CONFIGS])
+@pytest.mark.parametrize("cfg", CONFIGS, ids=[f"x{p}-{s}-b{b}-f{f}" for p, s, b, f in CONFIGS])
 @pytest.mark.parametrize("prec", ["bf16", "fp32"])
 def test_forced_config_all_pairs(cl, ens_1100, cfg, prec):
     if prec == "fp32" and cfg[0] == 4:
         pytest.skip("products apply to split-BF16 only")
     x, want = ens_1100
-    say(f"[config] N=1100 L=77 {prec} products={cfg[0]} {cfg[1]} band={cfg[2]}")
+    say(f"[config] N=1100 L=77 {prec} products={cfg[0]} {cfg[1]} band={cfg[2]} frame={cfg[3]}")
     cl.force_config(*cfg)
     try:
         got = cl.crmsd_matrix(dev(x), prec).cpu().numpy().astype(np.float64)
@@ -63,7 +64,8 @@ def test_forced_config_all_pairs(cl, ens_1100, cfg, prec):
     assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("cfg", [(3, "persistent", 8), (4, "persistent", 16), (4, "staged", 3)])
+@pytest.mark.parametrize("cfg", [(3, "persistent", 8, 1), (4, "persistent", 16, 0),
+                                 (4, "staged", 3, 1), (3, "staged", 16, 1)])
 def test_forced_config_cross(cl, cfg):
     say(f"[config] cross Na=200 Nb=97 L=64 bf16 {cfg}")
     x = synth.make_ensemble(515, 297, 64, sigma=(0.3, 4.0))
@@ -99,8 +101,9 @@ def check_batch_against_single(cl, ens, prec):
         assert torch.equal(single, part.cpu()), e.shape
 
 
-@pytest.mark.parametrize("cfg", [(3, "staged", 16), (4, "staged", 8), (3, "persistent", 16),
-                                 (4, "persistent", 3)])
+@pytest.mark.parametrize("cfg", [(3, "staged", 16, 1), (4, "staged", 8, 0),
+                                 (3, "persistent", 16, 1), (4, "persistent", 3, 1),
+                                 (3, "staged", 16, 0)])
 @pytest.mark.parametrize("prec", ["bf16", "fp32"])
 def test_forced_config_batch(cl, cfg, prec):
     if prec == "fp32" and cfg[0] == 4:
@@ -117,14 +120,15 @@ def test_forced_config_batch(cl, cfg, prec):
 def test_mixed_table_batch(cl, tmp_path):
     """A table that gives short models three products and the staged schedule
     and long ones four products: one batch then mixes both product counts;
-    every ensemble must equal its single call under the same table."""
+    every ensemble must equal its single call under the same table (the
+    reference frame is on for some ensembles and off for others)."""
     entries = []
     for nb in range(3):
         for lb in range(3):
             entries.append({"precision": "split_bf16", "n_bucket": nb, "l_bucket": lb,
                             "products": 4 if lb >= 1 else 3,
                             "schedule": "persistent" if nb == 1 else "staged",
-                            "band": [16, 8, 3][lb]})
+                            "band": [16, 8, 3][lb], "frame": (nb + lb) % 2})
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     p = tmp_path / "mixed.json"
     p.write_text(json.dumps({"arch": arch, "n_edges": [2, 64, 160], "l_edges": [1, 60, 200],

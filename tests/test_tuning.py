@@ -11,7 +11,8 @@ from paper_1302_4000_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COMMITTED = os.path.join(ROOT, "paper_1302_4000_amd", "tuning", "gfx950.json")
-DEFAULT = {"products": 3, "schedule": "staged", "band": 16, "source": "default", "bucket": -1}
+DEFAULT = {"products": 3, "schedule": "staged", "band": 16, "frame": 1, "source": "default",
+           "bucket": -1}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -36,9 +37,12 @@ def write(tmp_path, obj, name="t.json"):
     return str(p)
 
 
-def entry(prec, nb, lb, products=3, schedule="staged", band=16):
-    return {"precision": prec, "n_bucket": nb, "l_bucket": lb, "products": products,
-            "schedule": schedule, "band": band, "ms": {"ignored": 1.0}}
+def entry(prec, nb, lb, products=3, schedule="staged", band=16, frame=None):
+    e = {"precision": prec, "n_bucket": nb, "l_bucket": lb, "products": products,
+         "schedule": schedule, "band": band, "ms": {"ignored": 1.0}}
+    if frame is not None:
+        e["frame"] = frame
+    return e
 
 
 def test_no_table_gives_default():
@@ -50,20 +54,20 @@ def test_no_table_gives_default():
 
 
 def test_lookup_by_bucket(tmp_path):
-    t = table([entry("split_bf16", 0, 0, 4, "persistent", 8),
+    t = table([entry("split_bf16", 0, 0, 4, "persistent", 8, frame=0),
                entry("split_bf16", 2, 1, 4, "staged", 32),
-               entry("fp32", 1, 1, 3, "persistent", 24)])
+               entry("fp32", 1, 1, 3, "persistent", 24, frame=1)])
     binding.load_tuning(write(tmp_path, t))
     assert binding.tuning_path().endswith("t.json")
     # bucket 0 of N: [2, 256); bucket 0 of L: [1, 128)
     c = binding.get_config(100, 50, "bf16")
-    assert c == {"products": 4, "schedule": "persistent", "band": 8, "source": "table",
-                 "bucket": 0}
+    assert c == {"products": 4, "schedule": "persistent", "band": 8, "frame": 0,
+                 "source": "table", "bucket": 0}
     assert binding.get_config(255, 127, "bf16")["band"] == 8
     # edges are inclusive lower bounds; the last bucket is open
     assert binding.get_config(256, 127, "bf16") == DEFAULT          # (1, 0): no entry
     c = binding.get_config(10 ** 6, 10 ** 4, "bf16")
-    assert (c["products"], c["band"], c["bucket"]) == (4, 32, 2 * 2 + 1)
+    assert (c["products"], c["band"], c["bucket"], c["frame"]) == (4, 32, 2 * 2 + 1, 1)
     c = binding.get_config(1024, 128, "fp32")
     assert c["schedule"] == "staged" and c["source"] == "default"   # fp32 entry is (1, 1)
     c = binding.get_config(300, 300, "fp32")
@@ -80,6 +84,7 @@ def test_lookup_by_bucket(tmp_path):
     json.dumps(table([entry("split_bf16", 3, 0)])),                              # bucket range
     json.dumps(table([entry("split_bf16", 0, 0, schedule="other")])),
     json.dumps(table([entry("split_bf16", 0, 0, band=0)])),
+    json.dumps(table([entry("split_bf16", 0, 0, frame=2)])),
     json.dumps(table([entry("fp64", 0, 0)])),                                    # no tile kernel
     json.dumps(table([], n_edges=(256, 2))),                                     # not ascending
     json.dumps(table([{"precision": "fp32", "n_bucket": 0}])),                   # incomplete
@@ -102,10 +107,11 @@ def test_missing_file_rejected(tmp_path):
 
 def test_force_overrides_table(tmp_path):
     binding.load_tuning(write(tmp_path, table([entry("split_bf16", 0, 0, 4, "persistent", 8)])))
-    binding.force_config(3, "staged", 24)
+    binding.force_config(3, "staged", 24, frame=0)
     assert binding.get_config(100, 50, "bf16") == {"products": 3, "schedule": "staged",
-                                                    "band": 24, "source": "forced",
+                                                    "band": 24, "frame": 0, "source": "forced",
                                                     "bucket": -1}
+    assert binding.get_config(100, 50, "fp64")["frame"] == 0
     assert binding.get_config(100, 50, "bf16x4")["products"] == 4
     binding.force_config(None)
     assert binding.get_config(100, 50, "bf16")["source"] == "table"
@@ -113,6 +119,8 @@ def test_force_overrides_table(tmp_path):
         binding.force_config(5, "staged", 16)
     with pytest.raises(binding.ClucsoError):
         binding.force_config(3, "staged", 0)
+    with pytest.raises(binding.ClucsoError):
+        binding.force_config(3, "staged", 16, frame=3)
 
 
 def test_committed_table_covers_every_bucket():
@@ -132,9 +140,12 @@ def test_committed_table_covers_every_bucket():
     name = {"fp32": "fp32", "split_bf16": "bf16", "split_fp16": "fp16", "split_bf16x4": "bf16x4"}
     for e in t["entries"]:
         key = f"x{e['products']}/{e['schedule']}/{e['band']}"
+        if "frame" in e:
+            key += f"/f{e['frame']}"
         assert key in e["ms"]
         assert e["ms"][key] <= min(e["ms"].values()) * 1.0201
         c = binding.get_config(e["N"], e["L"], name[e["precision"]])
-        assert (c["products"], c["schedule"], c["band"], c["source"]) == \
-            (e["products"], e["schedule"], e["band"], "table")
+        frame = e.get("frame", 1) if e["schedule"] == "staged" else 0
+        assert (c["products"], c["schedule"], c["band"], c["frame"], c["source"]) == \
+            (e["products"], e["schedule"], e["band"], frame, "table")
     binding.load_tuning(None)
