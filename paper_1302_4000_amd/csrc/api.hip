@@ -291,15 +291,15 @@ int arith_mode(int mode, const KernelCfg &c)
 }
 
 // The set's share of configuration c: the reference frame (reference
-// candidates: the first models of the set `own`, whose chosen index lives
-// in its workspace slot) and the flag coefficients.
+// candidates: the first models of the set `own`, whose moments live in its
+// workspace slot) and the flag coefficients.
 void configure_set(const KernelCfg &c, const FlagCoefs &f, const ModelSet &own, ModelSet &s)
 {
     s.frame = c.frame;
     s.ref_X = own.X;
     s.ref_N = own.N;
     s.ref_b = own.use_b;
-    s.refidx = own.refidx;
+    s.refinfo = own.refinfo;
     s.ref_own = &own == &s;
     s.fw = f.fw;
     s.fe = f.fe;
@@ -586,7 +586,7 @@ ModelSet make_set(int mode, int64_t X, int64_t N, int64_t L, int64_t model0, int
     s.U = (int64_t)take(o, sizeof(double) * 9 * s.Np);
     s.PT = (int64_t)take(o, sizeof(double) * 9 * s.Np);
     s.F = (int64_t)take(o, sizeof(double) * s.Np);
-    s.refidx = (int64_t)take(o, sizeof(int32_t));
+    s.refinfo = (int64_t)take(o, sizeof(double) * REF_INFO);
     s.ops = (int64_t)take(o, op_bytes_per_model(mode, s.Lp) * s.Np);
     return s;
 }

@@ -158,7 +158,7 @@ struct ModelSet {
     int64_t F;            // byte offset of the flag weights (double [Np], see Problem)
     int64_t ref_X;        // float offset of the reference candidates (models of L atoms)
     int64_t ref_N;        // models the candidates are taken from
-    int64_t refidx;       // byte offset of the chosen candidate's index (int32)
+    int64_t refinfo;      // byte offset of the candidates' moments (REF_INFO doubles)
     double fw, fe;        // flag weight F = fw W + fe E, W = sum |d|^2
     int32_t use_b;        // coordinates come from the second base pointer
     int32_t ref_b;        // the reference candidates come from the second base pointer
@@ -167,6 +167,12 @@ struct ModelSet {
 };
 
 constexpr int REF_CANDIDATES = 8;
+// Candidate moments of a set (doubles): L cRMSD^2 of every candidate pair,
+// then each candidate's centroid (3) and G = sum r r^T (9).
+constexpr int RI_PAIRS = REF_CANDIDATES * (REF_CANDIDATES - 1) / 2;
+constexpr int RI_CEN = RI_PAIRS;
+constexpr int RI_G = RI_CEN + 3 * REF_CANDIDATES;
+constexpr int REF_INFO = RI_G + 9 * REF_CANDIDATES;
 
 struct Problem {
     int64_t NA, NB, L, KB;

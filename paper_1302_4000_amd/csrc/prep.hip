@@ -34,6 +34,138 @@ __device__ __forceinline__ float bf16_bits_to_float(uint16_t b)
     return __uint_as_float((uint32_t)b << 16);
 }
 
+// Sums of N values over the wave, the N reductions interleaved (their
+// cross-lane steps overlap instead of queueing behind one another).
+template <int N>
+__device__ __forceinline__ void wave_sums(double (&v)[N])
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double t[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t[k] = __shfl_xor(v[k], o, 64);
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += t[k];
+    }
+}
+
+// Per model set that owns a reference (ModelSet::refinfo, doubles):
+//   [0, RI_PAIRS)            L cRMSD^2 of candidate pairs (p, q), p < q, in
+//                            row-major order over all REF_CANDIDATES slots
+//   [RI_CEN, RI_CEN + 3 K)   the candidates' centroids
+//   [RI_G, RI_G + 9 K)       their G = sum r r^T of the centred coordinates
+constexpr int REF_WAVES = RI_PAIRS + REF_CANDIDATES;   // one wave per pair / candidate
+
+// Reference candidates of every model set that owns a reference: the first
+// K = min(ref_N, REF_CANDIDATES) models.  Grid: sets x (REF_WAVES / 4)
+// workgroups of 4 waves; wave u < RI_PAIRS computes pair u's L cRMSD^2 by
+// Eq. 2 in FP64 from one pass of moments (any choice of reference gives the
+// same scores, so only its ranking matters), wave RI_PAIRS + k the centroid
+// and G of candidate k.
+__global__ __launch_bounds__(256) void ref_moments_kernel(PrepLaunch a)
+{
+    const int per = REF_WAVES / 4;
+    const ModelSet &s = a.table ? a.table[blockIdx.x / per] : a.set[blockIdx.x / per];
+    if (!s.frame || !s.ref_own) return;                  // uniform over the workgroup
+    const int lane = threadIdx.x & 63;
+    const int u = (int)(blockIdx.x % per) * 4 + (threadIdx.x >> 6);
+    const int64_t L = s.L;
+    const int K = (int)(s.ref_N < REF_CANDIDATES ? s.ref_N : REF_CANDIDATES);
+    const float *x0 = (s.ref_b ? a.XB : a.XA) + s.ref_X;
+    double *info = (double *)(a.ws + s.refinfo);
+    const double inv = 1.0 / (double)L;
+    if (u < RI_PAIRS) {
+        int p = 0, q = u;
+        while (q >= REF_CANDIDATES - 1 - p) {
+            q -= REF_CANDIDATES - 1 - p;
+            ++p;
+        }
+        q += p + 1;
+        if (q >= K) return;
+        const float *xp = x0 + p * L * 3, *xq = x0 + q * L * 3;
+        // sum x_p, sum x_q, sum x_p x_q^T, sum |x_p|^2, sum |x_q|^2
+        double m[17];
+#pragma unroll
+        for (int k = 0; k < 17; ++k) m[k] = 0.0;
+        for (int64_t l = lane; l < L; l += 64) {
+            double up[3], uq[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                up[c] = (double)xp[3 * l + c];
+                uq[c] = (double)xq[3 * l + c];
+                m[c] += up[c];
+                m[3 + c] += uq[c];
+                m[15] = fma(up[c], up[c], m[15]);
+                m[16] = fma(uq[c], uq[c], m[16]);
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) m[6 + 3 * i + j] = fma(up[i], uq[j], m[6 + 3 * i + j]);
+        }
+        wave_sums(m);
+        if (lane == 0) {
+            double h[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) h[3 * i + j] = m[6 + 3 * i + j] - m[i] * m[3 + j] * inv;
+            const double ep = m[15] - (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * inv;
+            const double eq = m[16] - (m[3] * m[3] + m[4] * m[4] + m[5] * m[5]) * inv;
+            info[u] = fmax(eq2_lrmsd2(h, ep, eq), 0.0);
+        }
+    } else {
+        const int k = u - RI_PAIRS;
+        if (k >= K) return;
+        const float *x = x0 + k * L * 3;
+        double c[3] = {0.0, 0.0, 0.0};
+        for (int64_t l = lane; l < L; l += 64)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) c[t] += (double)x[3 * l + t];
+        wave_sums(c);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) c[t] *= inv;
+        double g[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) g[t] = 0.0;
+        for (int64_t l = lane; l < L; l += 64) {
+            const double r[3] = {(double)x[3 * l] - c[0], (double)x[3 * l + 1] - c[1],
+                                 (double)x[3 * l + 2] - c[2]};
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) g[3 * i + j] = fma(r[i], r[j], g[3 * i + j]);
+        }
+        wave_sums(g);
+        if (lane < 3) info[RI_CEN + 3 * k + lane] = c[lane];
+        if (lane < 9) info[RI_G + 9 * k + lane] = g[lane];
+    }
+}
+
+// The chosen reference of a set: of the K candidates, the one whose squared
+// cRMSDs to the other K - 1 sum to the least (ties to the lowest index), so
+// that an outlier model is not the reference.  Every lane returns it.
+__device__ __forceinline__ int ref_choice(const double *info, int K, int lane)
+{
+    double sum = 0.0;
+    if (lane < K) {
+        int t = 0;
+        for (int p = 0; p < REF_CANDIDATES; ++p)
+            for (int q = p + 1; q < REF_CANDIDATES; ++q, ++t)
+                if (q < K && (p == lane || q == lane)) sum += info[t];
+    }
+    int best = 0;
+    double bsum = __shfl(sum, 0, 64);
+    for (int k = 1; k < K; ++k) {
+        const double v = __shfl(sum, k, 64);
+        if (v < bsum) {
+            bsum = v;
+            best = k;
+        }
+    }
+    return best;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 {
@@ -55,81 +187,69 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
     double *E = (double *)(a.ws + s.E);
     double *cen = (double *)(a.ws + s.cen);
     double *E64 = (double *)(a.ws + s.E64);
+    const bool frame = MODE != MODE_FP64 && s.frame != 0;
+    const double inv = 1.0 / (double)L;
 
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    // the reference (frame): the chosen candidate's coordinates, centroid
+    // and G from ref_moments_kernel
+    const float *xr = x;
+    double cr[3] = {0.0, 0.0, 0.0}, G[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) G[t] = 0.0;
+    if (frame) {
+        const double *info = (const double *)(a.ws + s.refinfo);
+        const int K = (int)(s.ref_N < REF_CANDIDATES ? s.ref_N : REF_CANDIDATES);
+        const int k = ref_choice(info, K, lane);
+        xr = (s.ref_b ? a.XB : a.XA) + s.ref_X + (int64_t)k * L * 3;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) cr[t] = info[RI_CEN + 3 * k + t];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) G[t] = info[RI_G + 9 * k + t];
+    }
+
+    // pass 1: the centroid and, in the frame, sum x r^T with r the centred
+    // reference (= sum (x - c) r^T, since sum r = 0)
+    double m1[12];
+#pragma unroll
+    for (int t = 0; t < 12; ++t) m1[t] = 0.0;
     if (real) {
         for (int64_t l = lane; l < L; l += 64) {
-            c0 += (double)x[3 * l];
-            c1 += (double)x[3 * l + 1];
-            c2 += (double)x[3 * l + 2];
+            double xv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xv[c] = (double)x[3 * l + c];
+                m1[c] += xv[c];
+            }
+            if (frame) {
+                double rv[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rv[c] = (double)xr[3 * l + c] - cr[c];
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) m1[3 + 3 * p + q] = fma(xv[p], rv[q], m1[3 + 3 * p + q]);
+            }
         }
-        const double inv = 1.0 / (double)L;
-        c0 = wave_sum(c0) * inv;
-        c1 = wave_sum(c1) * inv;
-        c2 = wave_sum(c2) * inv;
+        wave_sums(m1);
     }
+    const double c0 = m1[0] * inv, c1 = m1[1] * inv, c2 = m1[2] * inv;
     if (lane == 0) {
         cen[3 * m] = c0;
         cen[3 * m + 1] = c1;
         cen[3 * m + 2] = c2;
     }
-    // exact FP64 radius of the raw coordinates (used by the FP64 fix-up)
-    double e64 = 0.0;
-    if (real) {
-        for (int64_t l = lane; l < L; l += 64) {
-            const double d0 = (double)x[3 * l] - c0, d1 = (double)x[3 * l + 1] - c1,
-                         d2 = (double)x[3 * l + 2] - c2;
-            e64 += d0 * d0 + d1 * d1 + d2 * d2;
-        }
-        e64 = wave_sum(e64);
-    }
-    if (lane == 0) E64[m] = e64;
-    if (MODE == MODE_FP64) {
-        if (lane == 0) E[m] = 0.0;
-        return;
-    }
 
     // Reference frame: the rotation rot taking this model onto the reference
     // (the proper rotation maximising sum r . (rot a), i.e. the transpose of
-    // the trace-norm adjoint of sum a r^T), and G = sum r r^T.  A rotation
-    // that is not orthonormal to 1e-12 (degenerate correlations) is replaced
-    // by the identity: any rotation gives the same scores, only the size of
-    // the residuals depends on it.
-    const bool frame = s.frame != 0;
+    // the trace-norm adjoint of sum a r^T).  A rotation that is not
+    // orthonormal to 1e-12 (degenerate correlations) is replaced by the
+    // identity: any rotation gives the same scores, only the size of the
+    // residuals depends on it.
     double rot[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
-    double G[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double cr[3] = {0.0, 0.0, 0.0};
-    const float *xr = (s.ref_b ? a.XB : a.XA) + s.ref_X +
-                      (frame ? (int64_t)*(const int *)(a.ws + s.refidx) * L * 3 : 0);
     if (frame && real) {
-        for (int64_t l = lane; l < L; l += 64) {
-            cr[0] += (double)xr[3 * l];
-            cr[1] += (double)xr[3 * l + 1];
-            cr[2] += (double)xr[3 * l + 2];
-        }
-        const double inv = 1.0 / (double)L;
+        double hm[9], q[9];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) cr[c] = wave_sum(cr[c]) * inv;
-        double hm[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int64_t l = lane; l < L; l += 64) {
-            const double av[3] = {(double)x[3 * l] - c0, (double)x[3 * l + 1] - c1,
-                                  (double)x[3 * l + 2] - c2};
-            const double rv[3] = {(double)xr[3 * l] - cr[0], (double)xr[3 * l + 1] - cr[1],
-                                  (double)xr[3 * l + 2] - cr[2]};
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    hm[3 * p + q] = fma(av[p], rv[q], hm[3 * p + q]);
-                    G[3 * p + q] = fma(rv[p], rv[q], G[3 * p + q]);
-                }
-        }
-#pragma unroll
-        for (int u = 0; u < 9; ++u) {
-            hm[u] = wave_sum(hm[u]);
-            G[u] = wave_sum(G[u]);
-        }
-        double q[9];
+        for (int t = 0; t < 9; ++t) hm[t] = m1[3 + t];
         eq2_adjoint(hm, q);
         double dev = 0.0;
 #pragma unroll
@@ -149,22 +269,28 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
         }
     }
 
+    // pass 2: operands, and the sums m2 = [e64, e, w, P (9)]: e64 the exact
+    // FP64 radius of the raw coordinates (the fix-up's), e the radius of the
+    // model the contraction sees (reference + quantised residual), w that of
+    // the quantised residual, P = sum d r^T
     const int64_t R = m / ROWBLK;
     const int r = (int)(m % ROWBLK);
     const int64_t KB = s.KB;
     const double cc[3] = {c0, c1, c2};
-    // e: radius of the model the contraction sees (reference + quantised
-    // residual); w: of the quantised residual; pp: P = sum d r^T
-    double e = 0.0, w = 0.0;
-    double pp[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t l = lane; l < s.Lp; l += 64) {
+    double m2[12];
+#pragma unroll
+    for (int t = 0; t < 12; ++t) m2[t] = 0.0;
+    const int64_t Lend = MODE == MODE_FP64 ? L : s.Lp;
+    for (int64_t l = lane; l < Lend; l += 64) {
         const bool in = real && l < L;
         double av[3], rv[3], dv[3], qv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             av[c] = in ? (double)x[3 * l + c] - cc[c] : 0.0;
             rv[c] = (in && frame) ? (double)xr[3 * l + c] - cr[c] : 0.0;
+            m2[0] = fma(av[c], av[c], m2[0]);
         }
+        if (MODE == MODE_FP64) continue;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             dv[c] = frame ? fma(rot[3 * c], av[0], fma(rot[3 * c + 1], av[1], fma(rot[3 * c + 2], av[2], -rv[c])))
@@ -205,116 +331,31 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            w = fma(qv[c], qv[c], w);
+            m2[2] = fma(qv[c], qv[c], m2[2]);
             const double sv = rv[c] + qv[c];
-            e = fma(sv, sv, e);
+            m2[1] = fma(sv, sv, m2[1]);
 #pragma unroll
-            for (int t = 0; t < 3; ++t) pp[3 * c + t] = fma(qv[c], rv[t], pp[3 * c + t]);
+            for (int t = 0; t < 3; ++t) m2[3 + 3 * c + t] = fma(qv[c], rv[t], m2[3 + 3 * c + t]);
         }
     }
-    e = wave_sum(e);
-    w = wave_sum(w);
-    if (frame) {
-#pragma unroll
-        for (int u = 0; u < 9; ++u) pp[u] = wave_sum(pp[u]);
-    }
+    wave_sums(m2);
     if (lane == 0) {
-        E[m] = e;
-        ((double *)(a.ws + s.F))[m] = fma(s.fw, w, s.fe * e);
+        E64[m] = m2[0];
+        if (MODE == MODE_FP64) {
+            E[m] = 0.0;
+            return;
+        }
+        E[m] = m2[1];
+        ((double *)(a.ws + s.F))[m] = fma(s.fw, m2[2], s.fe * m2[1]);
         double *U = (double *)(a.ws + s.U) + 9 * m;
         double *PT = (double *)(a.ws + s.PT) + 9 * m;
 #pragma unroll
         for (int p = 0; p < 3; ++p)
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
-                U[3 * p + t] = (frame && real) ? G[3 * p + t] + pp[3 * p + t] : 0.0;
-                PT[3 * p + t] = (frame && real) ? pp[3 * t + p] : 0.0;
+                U[3 * p + t] = (frame && real) ? G[3 * p + t] + m2[3 + 3 * p + t] : 0.0;
+                PT[3 * p + t] = (frame && real) ? m2[3 + 3 * t + p] : 0.0;
             }
-    }
-}
-
-// Reference choice, one workgroup per model set that owns a reference: of
-// the first K = min(ref_N, REF_CANDIDATES) models, the one whose squared
-// cRMSDs to the other K - 1 sum to the least (Eq. 2 in FP64 on the centred
-// models; ties to the lowest index).  Its index goes to the workspace for
-// prep.  Any choice gives the same scores; a central one gives the smallest
-// residuals, hence the smallest contraction error.
-__global__ __launch_bounds__(256) void ref_select_kernel(PrepLaunch a)
-{
-    __shared__ double cen[REF_CANDIDATES][3], rad[REF_CANDIDATES];
-    __shared__ double lr2[REF_CANDIDATES * (REF_CANDIDATES - 1) / 2];
-    const ModelSet &s = a.table ? a.table[blockIdx.x] : a.set[blockIdx.x];
-    if (!s.frame || !s.ref_own) return;                  // uniform over the workgroup
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t L = s.L;
-    const int K = (int)(s.ref_N < REF_CANDIDATES ? s.ref_N : REF_CANDIDATES);
-    const float *x0 = (s.ref_b ? a.XB : a.XA) + s.ref_X;
-    for (int k = w; k < K; k += 4) {
-        const float *x = x0 + k * L * 3;
-        double c[3] = {0.0, 0.0, 0.0};
-        for (int64_t l = lane; l < L; l += 64)
-#pragma unroll
-            for (int u = 0; u < 3; ++u) c[u] += (double)x[3 * l + u];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) c[u] = wave_sum(c[u]) / (double)L;
-        double e = 0.0;
-        for (int64_t l = lane; l < L; l += 64)
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const double d = (double)x[3 * l + u] - c[u];
-                e = fma(d, d, e);
-            }
-        e = wave_sum(e);
-        if (lane == 0) {
-            cen[k][0] = c[0];
-            cen[k][1] = c[1];
-            cen[k][2] = c[2];
-            rad[k] = e;
-        }
-    }
-    __syncthreads();
-    const int npair = K * (K - 1) / 2;
-    for (int t = w; t < npair; t += 4) {
-        int p = 0, q = t;
-        while (q >= K - 1 - p) {
-            q -= K - 1 - p;
-            ++p;
-        }
-        q += p + 1;
-        const float *xp = x0 + p * L * 3, *xq = x0 + q * L * 3;
-        double h[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int64_t l = lane; l < L; l += 64) {
-            double u[3], v[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                u[c] = (double)xp[3 * l + c] - cen[p][c];
-                v[c] = (double)xq[3 * l + c] - cen[q][c];
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) h[3 * i + j] = fma(u[i], v[j], h[3 * i + j]);
-        }
-#pragma unroll
-        for (int u = 0; u < 9; ++u) h[u] = wave_sum(h[u]);
-        if (lane == 0) lr2[t] = fmax(eq2_lrmsd2(h, rad[p], rad[q]), 0.0);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int best = 0;
-        double bsum = 0.0;
-        for (int k = 0; k < K; ++k) {
-            double sum = 0.0;
-            int t = 0;
-            for (int p = 0; p < K; ++p)
-                for (int q = p + 1; q < K; ++q, ++t)
-                    if (p == k || q == k) sum += lr2[t];
-            if (k == 0 || sum < bsum) {
-                bsum = sum;
-                best = k;
-            }
-        }
-        *(int *)(a.ws + s.refidx) = best;
     }
 }
 
@@ -323,7 +364,7 @@ hipError_t launch_prep(const PrepLaunch &a, hipStream_t s)
     bool frame = a.table != nullptr;     // a batch: some set may use the frame
     for (int k = 0; k < (a.table ? 0 : a.nset); ++k) frame |= a.set[k].frame != 0;
     if (frame && a.mode != MODE_FP64)
-        ref_select_kernel<<<dim3((unsigned)a.nset), dim3(256), 0, s>>>(a);
+        ref_moments_kernel<<<dim3((unsigned)(a.nset * (REF_WAVES / 4))), dim3(256), 0, s>>>(a);
     dim3 grid((unsigned)a.total), block(64);
     switch (a.mode) {
     case MODE_FP32: prep_kernel<MODE_FP32><<<grid, block, 0, s>>>(a); break;

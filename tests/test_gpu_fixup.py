@@ -4,7 +4,10 @@ with ragged edges: a last block row/column of 6 models and a last atom chunk
 of 13 atoms.  Near-identical models (noise 0.02-0.06 A) put every pair far
 below the split-bf16 flag threshold, so every recomputed score must match
 the FP64 oracle to FP64 accuracy, in the packed matrix, the cross matrix,
-threshold emission and the batched call.
+threshold emission and the batched call.  The tests force the configuration
+that sends every such pair to the fix-up (three products, no reference
+frame): with the frame, or four products, the same pairs are accurate
+enough without it.
 """
 import numpy as np
 import pytest
@@ -26,7 +29,9 @@ def cl():
     import paper_1302_4000_amd as m
     for p, t in TOL.items():
         m.set_tolerance(p, t)
-    return m
+    m.force_config(3, "staged", 16, 0)
+    yield m
+    m.force_config(None)
 
 
 def say(*a):
