@@ -120,13 +120,18 @@ clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L
  *             report 3 (4 for SPLIT_BF16X4).
  *   schedule  CLUSCO_SCHED_STAGED: one 64x64 tile per 4-wave workgroup with
  *             operands staged in LDS; CLUSCO_SCHED_PERSISTENT: persistent
- *             8-wave workgroups alternating contraction and FP64 epilogue.
- *             Backward and threshold calls always use the staged schedule; a
- *             batched call uses the one most of its work prefers.
+ *             8-wave workgroups alternating contraction and FP64 epilogue,
+ *             operands straight from global memory (never with the frame).
+ *             Backward and threshold calls always use
+ *             the staged schedule; a batched call uses the one most of its
+ *             work prefers, the persistent one only when no ensemble of the
+ *             batch uses the frame (so each ensemble's scores equal those of
+ *             its single call).
  *   band      tile rows per band of the tile order (L2 reuse of operands).
  *   frame     1: every model is first superimposed onto a reference structure
- *             (the first model of the ensemble; of set A in a cross
- *             comparison) by its optimal rotation, and the MFMA contraction
+ *             (of the ensemble's first eight models, of set A's in a cross
+ *             comparison, the one whose squared cRMSDs to the others sum to
+ *             the least) by its optimal rotation, and the MFMA contraction
  *             runs on the residuals from the reference; the large per-model
  *             terms of the correlation are added back in FP64.  Rotating a
  *             model leaves its scores unchanged (Eq. 1), while the

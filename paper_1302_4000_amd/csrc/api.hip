@@ -910,25 +910,29 @@ size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<M
     std::vector<Problem> P;
     int64_t model0 = 0;
     // each problem takes its bucket's configuration; the launch takes the
-    // schedule that most of the work (tiles x K-blocks x products) prefers,
-    // and under the persistent schedule no problem uses the reference frame
+    // schedule that most of the work (tiles x K-blocks x products) prefers
+    // among those that keep every problem's own arithmetic: the persistent
+    // schedule has no reference frame, so it is out when a problem uses the
+    // frame (every ensemble's scores then equal those of its single call)
     std::vector<KernelCfg> cfg(b.E);
     double vote[2] = {0.0, 0.0};
+    bool framed = false;
     for (int32_t e = 0; e < b.E; ++e) {
         if (b.N[e] < 2) continue;
         cfg[e] = config_for(h, mode, b.N[e], b.L[e]);
+        framed = framed || cfg[e].frame;
         const int64_t nb = round_up(b.N[e], TILE) / TILE;
-        vote[cfg[e].schedule == SCHED_PERSISTENT] += (double)tri_count(nb) *
+        vote[cfg[e].schedule] += (double)tri_count(nb) *
             (double)round_up(b.L[e], kblock(mode)) * (double)cfg[e].products;
     }
-    const int sched = vote[1] > vote[0] ? SCHED_PERSISTENT : SCHED_STAGED;
+    const int sched = !framed && vote[SCHED_PERSISTENT] > vote[SCHED_STAGED] ? SCHED_PERSISTENT
+                                                                             : SCHED_STAGED;
     int nx4 = 0;
     for (int32_t e = 0; e < b.E; ++e) {
         if (b.N[e] < 2) continue;
         ModelSet s = make_set(mode, b.coff ? b.coff[e] : 0, b.N[e], b.L[e], model0, 0, o);
         model0 += s.Np;
-        KernelCfg c = cfg[e];
-        if (sched == SCHED_PERSISTENT) c.frame = 0;
+        const KernelCfg c = cfg[e];
         const int am = arith_mode(mode, c);
         const FlagCoefs f = flag_coefs(h, mode, am, b.L[e]);
         configure_set(c, f, s, s);            // the reference is one of the ensemble's models

@@ -118,17 +118,20 @@ def test_forced_config_batch(cl, cfg, prec):
 
 
 def test_mixed_table_batch(cl, tmp_path):
-    """A table that gives short models three products and the staged schedule
-    and long ones four products: one batch then mixes both product counts;
-    every ensemble must equal its single call under the same table (the
-    reference frame is on for some ensembles and off for others)."""
+    """A table that gives short models three products and long ones four,
+    the staged schedule with the reference frame to two buckets and the
+    persistent one (no frame) to the rest: one batch then mixes both product
+    counts, and most of its work prefers the persistent schedule, which the
+    framed ensembles rule out; every ensemble must equal its single call
+    under the same table (the batch's schedule never changes an ensemble's
+    arithmetic)."""
     entries = []
     for nb in range(3):
         for lb in range(3):
             entries.append({"precision": "split_bf16", "n_bucket": nb, "l_bucket": lb,
                             "products": 4 if lb >= 1 else 3,
-                            "schedule": "persistent" if nb == 1 else "staged",
-                            "band": [16, 8, 3][lb], "frame": (nb + lb) % 2})
+                            "schedule": "staged" if nb == lb < 2 else "persistent",
+                            "band": [16, 8, 3][lb], "frame": 1})
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     p = tmp_path / "mixed.json"
     p.write_text(json.dumps({"arch": arch, "n_edges": [2, 64, 160], "l_edges": [1, 60, 200],
@@ -137,9 +140,11 @@ def test_mixed_table_batch(cl, tmp_path):
     cl.load_tuning(str(p))
     try:
         ens = batch()
-        kinds = {cl.get_config(e.shape[0], e.shape[1], "bf16")["products"] for e in ens}
+        cfgs = [cl.get_config(e.shape[0], e.shape[1], "bf16") for e in ens if e.shape[0] > 1]
+        kinds = {c["products"] for c in cfgs}
         say(f"[config] mixed-table batch of {len(ens)}: product counts {sorted(kinds)}")
         assert kinds == {3, 4}
+        assert {(c["schedule"], c["frame"]) for c in cfgs} == {("staged", 1), ("persistent", 0)}
         check_batch_against_single(cl, ens, "bf16")
     finally:
         cl.load_tuning(saved or None)

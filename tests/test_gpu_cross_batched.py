@@ -106,3 +106,47 @@ def test_batched_graph_replay_is_stable(cl):
     out2 = cl.crmsd_batched(b, flat.clone(), "bf16")
     torch.cuda.synchronize()
     assert torch.equal(out2, ref)
+
+
+@pytest.fixture(scope="module")
+def full_batch():
+    """The 64 uneven ensembles of the batched workload at full size (N ~
+    logU[100, 2000], L ~ logU[50, 500]) and, per ensemble, a pair sample:
+    300 uniform pairs plus its first row and its last column."""
+    ens = synth.make_batch()
+    rng = np.random.default_rng(23)
+    samples = []
+    for e in ens:
+        n = e.shape[0]
+        i = rng.integers(0, n, 300)
+        j = rng.integers(0, n, 300)
+        k = i != j
+        I = np.r_[np.minimum(i, j)[k], np.zeros(n - 1, np.int64), np.arange(n - 1)]
+        J = np.r_[np.maximum(i, j)[k], np.arange(1, n), np.full(n - 1, n - 1)]
+        samples.append((I, J, oracle.crmsd_pairs(e, I, J)))
+    return ens, samples
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp16", "bf16x4"])
+def test_batched_full_size_sampled(cl, full_batch, prec):
+    """The full 64-ensemble batch under the committed tuning table (its
+    ensembles take different kernel configurations) against the oracle on
+    each ensemble's pair sample; the longest models (L up to 500) are where
+    the contraction error is largest."""
+    ens, samples = full_batch
+    say(f"[batched] full size: {len(ens)} ensembles, "
+        f"N {min(e.shape[0] for e in ens)}..{max(e.shape[0] for e in ens)}, "
+        f"L {min(e.shape[1] for e in ens)}..{max(e.shape[1] for e in ens)}, {prec}")
+    tol = TOL.get(prec, 5e-4)
+    cl.set_tolerance(prec, tol)
+    b = cl.Batch([e.shape[:2] for e in ens])
+    flat = b.pack([torch.from_numpy(e) for e in ens], "cuda")
+    out = cl.crmsd_batched(b, flat, prec)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for e, (I, J, want), part in zip(ens, samples, b.split(out)):
+        got = part[torch.from_numpy(oracle.packed_index(I, J, e.shape[0])).cuda()]
+        err = float(np.abs(got.cpu().numpy().astype(np.float64) - want).max())
+        worst = max(worst, err)
+        assert err < tol, (e.shape, err)
+    say(f"  max err {worst:.3e} A over {sum(len(s[0]) for s in samples)} pairs")
