@@ -60,13 +60,18 @@ __device__ __forceinline__ double rsqrt_refined(double x)
     return fma(r, fma(-hr, r, 0.5), r);
 }
 
-// One Newton step on f(l) = l^3 - c2 l^2 + c1 l - c0.  An approximate
-// reciprocal of the slope only slows the contraction by its own relative
-// error (~1e-8), far below the quadratic gain.  Returns the step taken.
+// One Newton step on f(l) = l^3 - c2 l^2 + c1 l - c0.  With d = l - c2 and
+// g = d l + c1 (so f = g l - c0), the slope is f'(l) = 3 l^2 - 2 c2 l + c1
+// = g + l (l + d): five FP64 operations for f and f' together.  An
+// approximate reciprocal of the slope only slows the contraction by its own
+// relative error (~1e-8), far below the quadratic gain.  Returns the step
+// taken.
 __device__ __forceinline__ double eq2_newton(double &l, double c2, double c1, double c0)
 {
-    const double f = fma(fma(l - c2, l, c1), l, -c0);
-    const double fp = fma(fma(3.0, l, -2.0 * c2), l, c1);
+    const double d = l - c2;
+    const double g = fma(d, l, c1);
+    const double f = fma(g, l, -c0);
+    const double fp = fma(l, l + d, g);
     const double step = fp > 0.0 ? f * __builtin_amdgcn_rcp(fp) : 0.0;
     l -= step;
     return step;
@@ -121,14 +126,14 @@ __device__ __forceinline__ double eq2_lrmsd2(const double h[9], double EA, doubl
 // dependency chains sit side by side.  Instead of branches and selects on
 // degenerate inputs, three floors keep every operation finite: the slope in
 // the Newton step (at least 1e-30 c2^2, so a step at an exact double root is
-// 0/tiny = 0), the root (at least c2/3 and 1e-300, so 1/sqrt never sees 0)
+// 0/tiny = 0), the root (at least max(c2, 1e-300)/3, so 1/sqrt never sees 0)
 // and (s2 + S s3)^2 (at least 1e-300).  For H = 0 the sum then comes out as
 // about 1e-150 instead of 0, far below the score's resolution.
 template <int NP, int STEPS>
 __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const double (&ea)[NP],
                                                  const double (&eb)[NP], double (&out)[NP])
 {
-    double c2[NP], c1[NP], c0[NP], det[NP], l[NP], step[NP], m2c2[NP], floor_fp[NP];
+    double c2[NP], c1[NP], c0[NP], det[NP], l[NP], step[NP], c2f[NP], floor_fp[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const Eq2Coef c = eq2_coefficients(h[p]);
@@ -136,17 +141,20 @@ __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const
         c1[p] = c.c1;
         det[p] = c.det;
         c0[p] = c.det * c.det;
-        m2c2[p] = -2.0 * c.c2;
+        c2f[p] = fmax(c.c2, 1e-300);
         floor_fp[p] = fmax(1e-30 * (c.c2 * c.c2), 1e-300);
-        l[p] = fma(-c.c1, __builtin_amdgcn_rcp(fmax(c.c2, 1e-300)), c.c2);
+        l[p] = fma(-c.c1, __builtin_amdgcn_rcp(c2f[p]), c.c2);
         step[p] = 0.0;
     }
 #pragma unroll
     for (int it = 0; it < STEPS; ++it) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const double f = fma(fma(l[p] - c2[p], l[p], c1[p]), l[p], -c0[p]);
-            const double fp = fma(fma(3.0, l[p], m2c2[p]), l[p], c1[p]);
+            // f and f' as in eq2_newton
+            const double d = l[p] - c2[p];
+            const double g = fma(d, l[p], c1[p]);
+            const double f = fma(g, l[p], -c0[p]);
+            const double fp = fma(l[p], l[p] + d, g);
             step[p] = f * __builtin_amdgcn_rcp(fmax(fp, floor_fp[p]));
             l[p] -= step[p];
         }
@@ -158,8 +166,11 @@ __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         if (fabs(step[p]) > done_below * l[p]) {
-            for (int it = 0; it < 60 && fabs(step[p]) > 1e-15 * l[p]; ++it)
+            int it = 0;
+#pragma clang loop unroll(disable)
+            do {
                 step[p] = eq2_newton(l[p], c2[p], c1[p], c0[p]);
+            } while (++it < 60 && fabs(step[p]) > 1e-15 * l[p]);
         }
     }
     // The hardware reciprocal square roots (relative error below 6e-8 on
@@ -169,7 +180,7 @@ __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const
     // radii only).
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const double l1 = fmax(l[p], fmax(c2[p] * (1.0 / 3.0), 1e-300));
+        const double l1 = fmax(l[p], c2f[p] * (1.0 / 3.0));
         const double r1 = rsqrt_refined(l1);
         const double t = fma(2.0 * det[p], r1, c2[p] - l1);        // (s2 + S s3)^2
         const double tp = fmax(t, 1e-300);

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(FIX_THREADS) void fixup_kernel(FixupLaunch a)
                     need = (a.emit.masks[32 * t + (q >> 5)] >> (q & 31)) & 1u;
                 } else {
                     const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
-                    need = (double)out[k] < FA[i] + FB[j];
+                    need = flag_pair(out[k], (float)FA[i], (float)FB[j]);
                 }
                 if (need) todo[atomicAdd(&cnt, 1)] = (uint16_t)q;
             }
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(FIX_DTHREADS, FIX_DWAVES) void fixup_dense_kernel(F
                 const bool live = p.sym ? (i < j && j < NA) : (i < NA && j < NB);
                 if (live) {
                     const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
-                    c = (double)out[k] < FA[i] + FB[j] ? FIX_SAMPLE : 0;
+                    c = flag_pair(out[k], (float)FA[i], (float)FB[j]) ? FIX_SAMPLE : 0;
                 }
             }
             if (c) atomicAdd(&cnt, c);
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(FIX_DTHREADS, FIX_DWAVES) void fixup_dense_kernel(F
                     need = (a.emit.masks[32 * t + (q >> 5)] >> (q & 31)) & 1u;
                 } else {
                     const int64_t k = p.sym ? packed_index(i, j, NA) : i * NB + j;
-                    need = (double)out[k] < FA[i] + FB[j];
+                    need = flag_pair(out[k], (float)FA[i], (float)FB[j]);
                 }
                 if (need) todo[atomicAdd(&cnt, 1)] = (uint16_t)q;
             }

@@ -23,6 +23,8 @@
 // once per band, so wider bands fetch less until the band's row operands and
 // the columns in flight outgrow the XCD's 4 MB L2 (at N = 20,000, L = 150,
 // split-BF16: 8 rows fetched 0.77 GB per launch, 16 rows 0.44 GB).
+#include <algorithm>
+
 #include "eq2.h"
 #include "internal.h"
 
@@ -215,7 +217,8 @@ __device__ __forceinline__ WaveJob decode_job(const TileLaunch &a, int64_t t, in
 // j = Rb*32 + lane%32, and of row Ra*32 + lane%32, from which each pair takes
 // its row's values with a cross-lane shuffle.
 struct EpiRadii {
-    double ej, erow, fj, frow;
+    double ej, erow;
+    float fj, frow;
 };
 
 __device__ __forceinline__ EpiRadii epi_radii(const TileLaunch &a, const Problem &p,
@@ -226,7 +229,7 @@ __device__ __forceinline__ EpiRadii epi_radii(const TileLaunch &a, const Problem
     const double *FA = (const double *)(a.ws + p.FA);
     const double *FB = (const double *)(a.ws + p.FB);
     const int64_t j = job.Rb * ROWBLK + (lane & 31), i = job.Ra * ROWBLK + (lane & 31);
-    return EpiRadii{EB[j], EA[i], FB[j], FA[i]};
+    return EpiRadii{EB[j], EA[i], (float)FB[j], (float)FA[i]};
 }
 
 // E of row Ra*32 + r (r < 32) from the lane that loaded it.
@@ -235,8 +238,8 @@ __device__ __forceinline__ double row_radius(const EpiRadii &er, int r)
     return __shfl(er.erow, r, 64);
 }
 
-// F of row Ra*32 + r.
-__device__ __forceinline__ double row_flag(const EpiRadii &er, int r)
+// F of row Ra*32 + r (rounded to float: the flag test is flag_pair).
+__device__ __forceinline__ float row_flag(const EpiRadii &er, int r)
 {
     return __shfl(er.frow, r, 64);
 }
@@ -269,7 +272,7 @@ struct FrameTerms {
 // work runs without divergent branches.  urow: the U values of the wave's 32
 // rows (reference frame).  A pair is listed for the FP64 fix-up when its
 // score is below F_i + F_j and the problem runs the fix-up.
-template <bool FRAME>
+template <bool FRAME, bool SYM>
 __device__ __forceinline__ void epilogue_t(const TileLaunch &a, const Problem &p,
                                            const WaveJob &job, int lane, const f32x16 acc[9],
                                            const EpiRadii &er, const FrameTerms &ft)
@@ -279,15 +282,20 @@ __device__ __forceinline__ void epilogue_t(const TileLaunch &a, const Problem &p
     const double invL = 1.0 / (double)p.L;
     const bool fix = p.flag_coef > 0.0;
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
-    const double Ej = er.ej, Fj = er.fj;
-    const bool jlive = j < (p.sym ? NA : NB);
+    const double Ej = er.ej;
+    const float Fj = er.fj;
+    const bool jlive = j < (SYM ? NA : NB);
     const double *pcol = ft.pcol + 9 * (lane & 31);
-    bool flagged = false;
+    // the flag is folded in pair by pair into a wave-wide mask (scalar ALU):
+    // the empty asm keeps the compiler from deferring all sixteen comparisons
+    // to the end of the block, which would hold every score and row weight in
+    // registers until then
+    uint64_t flagged = 0;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int64_t i0 = job.Ra * ROWBLK + 8 * g + 4 * (lane >> 5);
         // row base k(i, j) - j: packed rows advance by N - i - 2, dense by NB
-        int64_t base = p.sym ? i0 * (2 * NA - i0 - 1) / 2 - i0 - 1 : i0 * NB;
+        int64_t base = SYM ? i0 * (2 * NA - i0 - 1) / 2 - i0 - 1 : i0 * NB;
 #pragma unroll
         for (int q0 = 0; q0 < 4; q0 += EPI_NP) {
             double h[EPI_NP][9], ei[EPI_NP], ej[EPI_NP], lr2[EPI_NP];
@@ -305,26 +313,33 @@ __device__ __forceinline__ void epilogue_t(const TileLaunch &a, const Problem &p
                 // hardware square root (within 1 ulp): the score's tolerance is
                 // orders of magnitude above float rounding
                 const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[b] * invL, 0.0));
-                const bool live = jlive && (p.sym ? i < j : i < NA);
+                const bool live = jlive && (SYM ? i < j : i < NA);
                 if (live) out[base + j] = v;
-                const double fi = row_flag(er, 8 * g + 4 * (lane >> 5) + q0 + b);
-                flagged |= fix && live && (double)v < fi + Fj;
-                base += p.sym ? NA - i - 2 : NB;
+                const float fi = row_flag(er, 8 * g + 4 * (lane >> 5) + q0 + b);
+                flagged |= __ballot(fix && live && flag_pair(v, fi, Fj));
+                asm volatile("" : "+s"(flagged));
+                // the next row's base, kept incremental (the empty asm stops
+                // the compiler from re-deriving it with a multiplication)
+                base += SYM ? NA - i - 2 : NB;
+                asm volatile("" : "+v"(base));
             }
         }
     }
-    if (__any(flagged) && lane == 0) {
+    if (flagged != 0 && lane == 0) {
         const int s = atomicAdd(&a.counters[0], 1);
         a.list[s] = FixEntry{(uint32_t)job.pidx, ((uint32_t)job.Ra << 16) | (uint32_t)job.Rb};
     }
 }
 
+// SYM: the problem is one ensemble against itself (packed upper triangle);
+// else a cross comparison (dense NA x NB).
+template <bool SYM>
 __device__ __forceinline__ void epilogue(const TileLaunch &a, const Problem &p,
                                          const WaveJob &job, int lane, const f32x16 acc[9],
                                          const EpiRadii &er, const FrameTerms &ft)
 {
-    if (p.frame) epilogue_t<true>(a, p, job, lane, acc, er, ft);
-    else epilogue_t<false>(a, p, job, lane, acc, er, ft);
+    if (p.frame) epilogue_t<true, SYM>(a, p, job, lane, acc, er, ft);
+    else epilogue_t<false, SYM>(a, p, job, lane, acc, er, ft);
 }
 
 // Backward epilogue: per live pair, w = g / (L cRMSD) (0 where the score
@@ -403,7 +418,8 @@ __device__ __forceinline__ void thr_scores_t(const TileLaunch &a, const Problem 
     const bool fix = p.flag_coef > 0.0;
     const float cutoff = (float)a.emit.cutoff;
     const int64_t j = job.Rb * ROWBLK + (lane & 31);
-    const double Ej = er.ej, Fj = er.fj;
+    const double Ej = er.ej;
+    const float Fj = er.fj;
     const bool jlive = j < NA;
     const double *pcol = ft.pcol + 9 * (lane & 31);
     uint32_t emit = 0, flag = 0;
@@ -419,7 +435,7 @@ __device__ __forceinline__ void thr_scores_t(const TileLaunch &a, const Problem 
         eq2_lrmsd2_batch<1, EPI_STEPS>(h, ei, ej, lr2);   // the forward's arithmetic
         const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[0] * invL, 0.0));
         const bool live = jlive && i < j;
-        const bool fl = fix && live && (double)v < row_flag(er, rr) + Fj;
+        const bool fl = fix && live && flag_pair(v, row_flag(er, rr), Fj);
         tp.vs[r] = v;
         flag |= (uint32_t)fl << r;
         emit |= (uint32_t)(live && !fl && v < cutoff) << r;
@@ -553,7 +569,7 @@ __global__ __launch_bounds__(512, 1) void tile_kernel(TileLaunch a)
             const Problem &pe = problem_of<KIND>(a, job.pidx);
             const EpiRadii er = epi_radii(a, pe, job, lane);
             const FrameTerms ft{nullptr, nullptr};
-            if constexpr (OP == OP_FWD) epilogue_t<false>(a, pe, job, lane, acc, er, ft);
+            if constexpr (OP == OP_FWD) epilogue_t<false, KIND != TK_RECT>(a, pe, job, lane, acc, er, ft);
             else if constexpr (OP == OP_BWD) bwd_epilogue(a, pe, job, lane, acc, er);
             else thr_epilogue(a, pe, job, lane, acc, er, ft);
             job.active = 0;
@@ -631,31 +647,17 @@ __device__ __forceinline__ void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// One 64x64 tile t (launch-relative) by the workgroup's four waves, with
+// the three ring slots of the workgroup.  The slots are separate arrays
+// (fixed per unrolled step below), so that the compiler can tell the loads
+// in flight into one slot from the reads of another and adds no wait for
+// them.
 template <int MODE, int KIND, int OP>
-__global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
+__device__ __forceinline__ void staged_tile(const TileLaunch &a, int64_t t, int tid, int lane, int w,
+                                            u32x4 *slot0, u32x4 *slot1, u32x4 *slot2)
 {
     using G = StageGeom<MODE>;
-    // three ring slots as separate arrays (fixed per unrolled step below), so
-    // that the compiler can tell the loads in flight into one slot from the
-    // reads of another and adds no wait for them
-    __shared__ u32x4 slot0[G::SLOT], slot1[G::SLOT], slot2[G::SLOT];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wy = w >> 1, wx = w & 1;
-    // Workgroups are dealt to the XCDs round-robin.  One problem: tiles in
-    // banded order, one contiguous chunk per XCD.  A batch: the host's order
-    // (most expensive tiles first, for balance) in runs of eight consecutive
-    // tiles per XCD (within every 64 workgroups, XCD x takes tiles 8x..8x+7),
-    // so neighbouring tiles of one problem share an L2.
-    int64_t t;
-    if constexpr (KIND == TK_BATCH) {
-        const int64_t b = blockIdx.x;
-        t = (b & ~(int64_t)63) + 8 * (b & 7) + ((b >> 3) & 7);
-    } else {
-        const int64_t per_xcd = gridDim.x >> 3;
-        t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    }
-    if (t >= a.T) return;                          // uniform over the workgroup
     if constexpr (KIND == TK_BATCH) t += a.t0;
     int32_t e = 0;
     if constexpr (KIND == TK_BATCH)
@@ -810,7 +812,62 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
         }
     } else if (job.active) {
         if constexpr (OP == OP_BWD) bwd_epilogue(a, p, job, lane, acc, er);
-        else epilogue(a, p, job, lane, acc, er, ft);
+        else epilogue<KIND != TK_RECT>(a, p, job, lane, acc, er, ft);
+    }
+}
+
+template <int MODE, int KIND, int OP>
+__global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
+{
+    using G = StageGeom<MODE>;
+    __shared__ u32x4 slot0[G::SLOT], slot1[G::SLOT], slot2[G::SLOT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // Workgroups are dealt to the XCDs round-robin.  One problem: tiles in
+    // banded order, one contiguous chunk per XCD.  A batch: the host's order
+    // (most expensive tiles first, for balance) in runs of eight consecutive
+    // tiles per XCD (within every 64 workgroups, XCD x takes tiles 8x..8x+7),
+    // so neighbouring tiles of one problem share an L2.
+    int64_t t;
+    if constexpr (KIND == TK_BATCH) {
+        const int64_t b = blockIdx.x;
+        t = (b & ~(int64_t)63) + 8 * (b & 7) + ((b >> 3) & 7);
+    } else {
+        const int64_t per_xcd = gridDim.x >> 3;
+        t = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    }
+    if (t >= a.T) return;                          // uniform over the workgroup
+    staged_tile<MODE, KIND, OP>(a, t, tid, lane, w, slot0, slot1, slot2);
+}
+
+// ------------------------------------------------- looped staged forward
+//
+// The staged tile in a loop: two persistent 4-wave workgroups per CU, each
+// taking the tiles of its XCD's contiguous chunk of the tile order
+// round-robin.  The second half of each XCD's workgroups (the second
+// workgroup of a CU when the first round fills every CU once) starts about
+// one contraction later, so that the two workgroups of a CU run out of
+// phase: while one contracts on the matrix cores the other evaluates its
+// FP64 epilogue on the vector ALU.  Nothing else differs from the staged
+// kernel; results are identical.
+template <int MODE, int KIND>
+__global__ __launch_bounds__(256, 2) void staged_loop_kernel(TileLaunch a)
+{
+    using G = StageGeom<MODE>;
+    __shared__ u32x4 slot0[G::SLOT], slot1[G::SLOT], slot2[G::SLOT];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t per = gridDim.x >> 3;
+    const int64_t xcd = blockIdx.x & 7, jw = blockIdx.x >> 3;
+    const int64_t c0 = a.T * xcd / 8, c1 = a.T * (xcd + 1) / 8;
+    if (2 * jw >= per) __builtin_amdgcn_s_sleep(127);
+    for (int64_t t = c0 + jw; t < c1; t += per) {
+        // the thread index is made opaque per tile: values derived from it
+        // are then computed where they are used instead of being hoisted out
+        // of the loop, where they would hold registers through the tile
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        staged_tile<MODE, KIND, OP_FWD>(a, t, tid, tid & 63, w, slot0, slot1, slot2);
+        __syncthreads();                           // the ring is free for the next tile
     }
 }
 
@@ -832,18 +889,25 @@ static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, 
         else return hipErrorInvalidValue;
         return hipGetLastError();
     }
-    const bool pers = a.sched == SCHED_PERSISTENT;
+    const bool pers = a.sched == SCHED_PERSISTENT, loop = a.sched == SCHED_LOOPED;
+    // looped: two workgroups per CU (grid twice the persistent one, capped
+    // at the tile count rounded to the XCDs)
+    const int64_t lgrid = std::min<int64_t>(2 * grid, round_up(a.T > 0 ? a.T : 1, 8));
+    const dim3 lg((unsigned)lgrid);
     switch (a.kind) {
     case TK_SYM:
         if (pers) tile_kernel<MODE, TK_SYM, OP_FWD><<<g, b, 0, s>>>(a);
+        else if (loop) staged_loop_kernel<MODE, TK_SYM><<<lg, sb, 0, s>>>(a);
         else staged_kernel<MODE, TK_SYM, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
     case TK_RECT:
         if (pers) tile_kernel<MODE, TK_RECT, OP_FWD><<<g, b, 0, s>>>(a);
+        else if (loop) staged_loop_kernel<MODE, TK_RECT><<<lg, sb, 0, s>>>(a);
         else staged_kernel<MODE, TK_RECT, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
     case TK_BATCH:
         if (pers) tile_kernel<MODE, TK_BATCH, OP_FWD><<<g, b, 0, s>>>(a);
+        else if (loop) staged_loop_kernel<MODE, TK_BATCH><<<lg, sb, 0, s>>>(a);
         else staged_kernel<MODE, TK_BATCH, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
     default: return hipErrorInvalidValue;
