@@ -121,14 +121,11 @@ clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L
  *   schedule  CLUSCO_SCHED_STAGED: one 64x64 tile per 4-wave workgroup with
  *             operands staged in LDS; CLUSCO_SCHED_PERSISTENT: persistent
  *             8-wave workgroups alternating contraction and FP64 epilogue,
- *             operands straight from global memory (never with the frame);
- *             CLUSCO_SCHED_LOOPED: the staged tile in a loop, two persistent
- *             workgroups per CU started out of phase, so that one contracts
- *             while the other runs its epilogue.  Backward and threshold
- *             calls always use the staged schedule; a batched call uses the
- *             one most of its work prefers, the persistent one only when no
- *             ensemble of the batch uses the frame (so each ensemble's scores
- *             equal those of its single call).
+ *             operands straight from global memory (never with the frame).
+ *             Backward and threshold calls always use the staged schedule; a
+ *             batched call uses the one most of its work prefers, the
+ *             persistent one only when no ensemble of the batch uses the frame
+ *             (so each ensemble's scores equal those of its single call).
  *   band      tile rows per band of the tile order (L2 reuse of operands).
  *   frame     1: every model is first superimposed onto a reference structure
  *             (of the ensemble's first eight models, of set A's in a cross
@@ -153,16 +150,15 @@ clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L
  *   bucket bounds (bucket i: edges[i] <= x < edges[i+1], the last is open),
  *   "entries": [{"precision": "fp32" | "split_bf16" | "split_fp16" |
  *   "split_bf16x4", "n_bucket": i, "l_bucket": j, "products": 3 | 4,
- *   "schedule": "staged" | "persistent" | "looped", "band": 1..256, optionally
+ *   "schedule": "staged" | "persistent", "band": 1..256, optionally
  *   "frame": 0 | 1 (default 1), ...}]
  * (other keys are ignored). */
 #define CLUSCO_SCHED_STAGED 0
 #define CLUSCO_SCHED_PERSISTENT 1
-#define CLUSCO_SCHED_LOOPED 2
 
 typedef struct {
     int32_t products; /* 3 or 4 (see above) */
-    int32_t schedule; /* CLUSCO_SCHED_STAGED, _PERSISTENT or _LOOPED */
+    int32_t schedule; /* CLUSCO_SCHED_STAGED or CLUSCO_SCHED_PERSISTENT */
     int32_t band;     /* 1..256 */
     int32_t frame;    /* 1: contract residuals in the reference frame, 0: the models */
     int32_t source;   /* out: 0 built-in default, 1 tuning table, 2 forced */

@@ -20,7 +20,7 @@ OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = range(5)
 PRECISION = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2, "fp64": 3,
              "bf16x4": 4, "split_bf16x4": 4}
 
-SCHEDULES = {"staged": 0, "persistent": 1, "looped": 2}
+SCHEDULES = {"staged": 0, "persistent": 1}
 
 
 class Config(ctypes.Structure):

@@ -46,7 +46,7 @@ struct BatchPlan {
 // (precision, N bucket, L bucket).
 struct KernelCfg {
     int products = 3;               // split-BF16: MFMA products per K-block (3 or 4)
-    int schedule = SCHED_STAGED;    // SCHED_STAGED, SCHED_PERSISTENT or SCHED_LOOPED
+    int schedule = SCHED_STAGED;    // SCHED_STAGED or SCHED_PERSISTENT
     int band = 16;                  // tile rows per band of the tile order
     int frame = 1;                  // contract residuals in the reference frame
     int id = -1;                    // bucket index in the table (-1: not from the table)
@@ -500,10 +500,7 @@ clusco_status parse_tuning(const std::string &text, const std::string &arch, Tun
             t.nb = (int)nb->num;
             t.lb = (int)lb->num;
             t.cfg.products = (int)pd->num;
-            t.cfg.schedule = sc->str == "staged"       ? SCHED_STAGED
-                             : sc->str == "persistent" ? SCHED_PERSISTENT
-                             : sc->str == "looped"     ? SCHED_LOOPED
-                                                       : -1;
+            t.cfg.schedule = sc->str == "staged" ? SCHED_STAGED : sc->str == "persistent" ? SCHED_PERSISTENT : -1;
             t.cfg.band = (int)bd->num;
             const JVal *fr = e.get("frame");
             if (fr) t.cfg.frame = fr->kind == JVal::NUM && (fr->num == 0 || fr->num == 1) ? (int)fr->num : -1;
@@ -514,8 +511,8 @@ clusco_status parse_tuning(const std::string &text, const std::string &arch, Tun
         }
         if (!ok) {
             *err = "tuning file: bad entry (needs precision, n_bucket, l_bucket, products 3|4, "
-                   "schedule staged|persistent|looped, band 1..256, optional frame 0|1, "
-                   "buckets within the edges)";
+                   "schedule staged|persistent, band 1..256, optional frame 0|1, buckets "
+                   "within the edges)";
             return CLUSCO_ERR_INVALID_ARG;
         }
         out.entries.push_back(t);
@@ -918,7 +915,7 @@ size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<M
     // schedule has no reference frame, so it is out when a problem uses the
     // frame (every ensemble's scores then equal those of its single call)
     std::vector<KernelCfg> cfg(b.E);
-    double vote[3] = {0.0, 0.0, 0.0};
+    double vote[2] = {0.0, 0.0};
     bool framed = false;
     for (int32_t e = 0; e < b.E; ++e) {
         if (b.N[e] < 2) continue;
@@ -928,10 +925,8 @@ size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<M
         vote[cfg[e].schedule] += (double)tri_count(nb) *
             (double)round_up(b.L[e], kblock(mode)) * (double)cfg[e].products;
     }
-    if (framed) vote[SCHED_PERSISTENT] = -1.0;
-    int sched = SCHED_STAGED;
-    for (int k = 1; k < 3; ++k)
-        if (vote[k] > vote[sched]) sched = k;
+    const int sched = !framed && vote[SCHED_PERSISTENT] > vote[SCHED_STAGED] ? SCHED_PERSISTENT
+                                                                             : SCHED_STAGED;
     int nx4 = 0;
     for (int32_t e = 0; e < b.E; ++e) {
         if (b.N[e] < 2) continue;
@@ -1147,8 +1142,7 @@ clusco_status clusco_force_config(clusco_handle h, const clusco_config *cfg)
         h->forced = false;
     } else {
         if ((cfg->products != 3 && cfg->products != 4) ||
-            (cfg->schedule != CLUSCO_SCHED_STAGED && cfg->schedule != CLUSCO_SCHED_PERSISTENT &&
-             cfg->schedule != CLUSCO_SCHED_LOOPED) ||
+            (cfg->schedule != CLUSCO_SCHED_STAGED && cfg->schedule != CLUSCO_SCHED_PERSISTENT) ||
             cfg->band < 1 || cfg->band > 256 || (cfg->frame != 0 && cfg->frame != 1))
             return fail(h, CLUSCO_ERR_INVALID_ARG,
                         "need products 3 or 4, a known schedule, band in 1..256, frame 0 or 1");

@@ -199,10 +199,8 @@ struct Problem {
 // Tile schedules (a tuning choice per problem bucket).
 enum Schedule {
     SCHED_STAGED = 0,      // one 64x64 tile per 4-wave workgroup, operands staged in LDS
-    SCHED_PERSISTENT = 1,  // persistent 8-wave workgroups, contraction / epilogue ping-pong
+    SCHED_PERSISTENT = 1   // persistent 8-wave workgroups, contraction / epilogue ping-pong
                            // (operands from global memory, no reference frame)
-    SCHED_LOOPED = 2       // the staged tile in a loop, two persistent workgroups per CU
-                           // running out of phase (forward only)
 };
 
 // The fix-up flag of a pair: its score v is below F_i + F_j, the sum of the
@@ -267,7 +265,7 @@ struct TileLaunch {
     int32_t nprob;
     int32_t kind;         // TK_SYM, TK_RECT, TK_BATCH
     int64_t T;            // 64x64 tiles in the launch
-    int32_t sched;        // SCHED_STAGED, SCHED_PERSISTENT or SCHED_LOOPED (forward only)
+    int32_t sched;        // SCHED_STAGED or SCHED_PERSISTENT (forward only)
     int32_t ctr;          // TK_BATCH persistent: index of its work counter in counters
     int64_t t0;           // TK_BATCH: first tile of this launch (tiles t0 .. t0 + T - 1)
     int *counters;

@@ -23,8 +23,6 @@
 // once per band, so wider bands fetch less until the band's row operands and
 // the columns in flight outgrow the XCD's 4 MB L2 (at N = 20,000, L = 150,
 // split-BF16: 8 rows fetched 0.77 GB per launch, 16 rows 0.44 GB).
-#include <algorithm>
-
 #include "eq2.h"
 #include "internal.h"
 
@@ -840,37 +838,6 @@ __global__ __launch_bounds__(256, 2) void staged_kernel(TileLaunch a)
     staged_tile<MODE, KIND, OP>(a, t, tid, lane, w, slot0, slot1, slot2);
 }
 
-// ------------------------------------------------- looped staged forward
-//
-// The staged tile in a loop: two persistent 4-wave workgroups per CU, each
-// taking the tiles of its XCD's contiguous chunk of the tile order
-// round-robin.  The second half of each XCD's workgroups (the second
-// workgroup of a CU when the first round fills every CU once) starts about
-// one contraction later, so that the two workgroups of a CU run out of
-// phase: while one contracts on the matrix cores the other evaluates its
-// FP64 epilogue on the vector ALU.  Nothing else differs from the staged
-// kernel; results are identical.
-template <int MODE, int KIND>
-__global__ __launch_bounds__(256, 2) void staged_loop_kernel(TileLaunch a)
-{
-    using G = StageGeom<MODE>;
-    __shared__ u32x4 slot0[G::SLOT], slot1[G::SLOT], slot2[G::SLOT];
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t per = gridDim.x >> 3;
-    const int64_t xcd = blockIdx.x & 7, jw = blockIdx.x >> 3;
-    const int64_t c0 = a.T * xcd / 8, c1 = a.T * (xcd + 1) / 8;
-    if (2 * jw >= per) __builtin_amdgcn_s_sleep(127);
-    for (int64_t t = c0 + jw; t < c1; t += per) {
-        // the thread index is made opaque per tile: values derived from it
-        // are then computed where they are used instead of being hoisted out
-        // of the loop, where they would hold registers through the tile
-        int tid = (int)threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        staged_tile<MODE, KIND, OP_FWD>(a, t, tid, tid & 63, w, slot0, slot1, slot2);
-        __syncthreads();                           // the ring is free for the next tile
-    }
-}
-
 template <int MODE>
 static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, int op)
 {
@@ -889,25 +856,18 @@ static hipError_t launch_mode(const TileLaunch &a, hipStream_t s, int64_t grid, 
         else return hipErrorInvalidValue;
         return hipGetLastError();
     }
-    const bool pers = a.sched == SCHED_PERSISTENT, loop = a.sched == SCHED_LOOPED;
-    // looped: two workgroups per CU (grid twice the persistent one, capped
-    // at the tile count rounded to the XCDs)
-    const int64_t lgrid = std::min<int64_t>(2 * grid, round_up(a.T > 0 ? a.T : 1, 8));
-    const dim3 lg((unsigned)lgrid);
+    const bool pers = a.sched == SCHED_PERSISTENT;
     switch (a.kind) {
     case TK_SYM:
         if (pers) tile_kernel<MODE, TK_SYM, OP_FWD><<<g, b, 0, s>>>(a);
-        else if (loop) staged_loop_kernel<MODE, TK_SYM><<<lg, sb, 0, s>>>(a);
         else staged_kernel<MODE, TK_SYM, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
     case TK_RECT:
         if (pers) tile_kernel<MODE, TK_RECT, OP_FWD><<<g, b, 0, s>>>(a);
-        else if (loop) staged_loop_kernel<MODE, TK_RECT><<<lg, sb, 0, s>>>(a);
         else staged_kernel<MODE, TK_RECT, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
     case TK_BATCH:
         if (pers) tile_kernel<MODE, TK_BATCH, OP_FWD><<<g, b, 0, s>>>(a);
-        else if (loop) staged_loop_kernel<MODE, TK_BATCH><<<lg, sb, 0, s>>>(a);
         else staged_kernel<MODE, TK_BATCH, OP_FWD><<<sg, sb, 0, s>>>(a);
         break;
     default: return hipErrorInvalidValue;

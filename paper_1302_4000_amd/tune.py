@@ -11,9 +11,8 @@ clusco_force_config, and records the fastest:
 
   products   split-BF16 only: 3 or 4 MFMA products per K-block (4 costs a
              third more MFMA issue and leaves far fewer pairs to the fix-up)
-  schedule   staged (one tile per workgroup, LDS-staged operands),
-             persistent (ping-pong workgroups) or looped (the staged tile in
-             two persistent workgroups per CU, started out of phase)
+  schedule   staged (one tile per workgroup, LDS-staged operands) or
+             persistent (ping-pong workgroups)
   band       tile rows per band of the tile order (only where the tile grid
              is wider than a band)
   frame      contract the models (0) or their residuals from the reference
@@ -89,8 +88,8 @@ def candidates(prec, N):
     bands = [8, 16, 32] if nb > 16 else [16]
     prods = {"split_bf16": [3, 4], "split_bf16x4": [4]}.get(prec, [3])
     # the persistent schedule serves problems without the reference frame
-    return [(p, sch, b, f) for p in prods for sch in ("staged", "persistent", "looped")
-            for b in bands for f in ((0,) if sch == "persistent" else (0, 1))]
+    return [(p, sch, b, f) for p in prods for sch in ("staged", "persistent") for b in bands
+            for f in ((0, 1) if sch == "staged" else (0,))]
 
 
 def main(argv=None):

@@ -1,5 +1,5 @@
 """GPU parity of every kernel configuration the tuning table can choose
-(products 3 / 4 for split-BF16, staged / persistent / looped schedule, band widths,
+(products 3 / 4 for split-BF16, staged / persistent schedule, band widths,
 reference frame on / off) against the FP64 oracle, for single ensembles, cross comparisons and
 batches; a batch whose ensembles take different configurations (mixed
 product counts) must equal single calls made under the same table."""
@@ -15,8 +15,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-4, "bf16": 5e-4, "fp16": 1e-4, "bf16x4": 5e-4}
-CONFIGS = [(p, s, b, f) for p in (3, 4) for s in ("staged", "persistent", "looped")
-           for b in (8, 16, 3) for f in (0, 1)]
+CONFIGS = [(p, s, b, f) for p in (3, 4) for s in ("staged", "persistent") for b in (8, 16, 3)
+           for f in (0, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -65,8 +65,7 @@ def test_forced_config_all_pairs(cl, ens_1100, cfg, prec):
 
 
 @pytest.mark.parametrize("cfg", [(3, "persistent", 8, 1), (4, "persistent", 16, 0),
-                                 (4, "staged", 3, 1), (3, "staged", 16, 1),
-                                 (3, "looped", 16, 1), (4, "looped", 8, 0)])
+                                 (4, "staged", 3, 1), (3, "staged", 16, 1)])
 def test_forced_config_cross(cl, cfg):
     say(f"[config] cross Na=200 Nb=97 L=64 bf16 {cfg}")
     x = synth.make_ensemble(515, 297, 64, sigma=(0.3, 4.0))
@@ -104,8 +103,7 @@ def check_batch_against_single(cl, ens, prec):
 
 @pytest.mark.parametrize("cfg", [(3, "staged", 16, 1), (4, "staged", 8, 0),
                                  (3, "persistent", 16, 1), (4, "persistent", 3, 1),
-                                 (3, "staged", 16, 0), (3, "looped", 16, 1),
-                                 (4, "looped", 3, 0)])
+                                 (3, "staged", 16, 0)])
 @pytest.mark.parametrize("prec", ["bf16", "fp32"])
 def test_forced_config_batch(cl, cfg, prec):
     if prec == "fp32" and cfg[0] == 4:

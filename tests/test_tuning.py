@@ -57,7 +57,7 @@ def test_lookup_by_bucket(tmp_path):
     t = table([entry("split_bf16", 0, 0, 4, "persistent", 8, frame=0),
                entry("split_bf16", 2, 1, 4, "staged", 32),
                entry("fp32", 1, 1, 3, "persistent", 24, frame=1),
-               entry("split_fp16", 2, 0, 3, "looped", 8, frame=1)])
+               entry("split_fp16", 2, 0, 3, "staged", 8, frame=0)])
     binding.load_tuning(write(tmp_path, t))
     assert binding.tuning_path().endswith("t.json")
     # bucket 0 of N: [2, 256); bucket 0 of L: [1, 128)
@@ -73,10 +73,10 @@ def test_lookup_by_bucket(tmp_path):
     assert c["schedule"] == "staged" and c["source"] == "default"   # fp32 entry is (1, 1)
     c = binding.get_config(300, 300, "fp32")
     assert (c["schedule"], c["band"], c["source"]) == ("persistent", 24, "table")
-    # the looped schedule keeps the reference frame; the persistent one drops it
+    # the persistent schedule drops the reference frame; the staged one keeps the table's
     assert binding.get_config(300, 300, "fp32")["frame"] == 0
     c = binding.get_config(5000, 100, "fp16")
-    assert (c["schedule"], c["band"], c["frame"], c["source"]) == ("looped", 8, 1, "table")
+    assert (c["schedule"], c["band"], c["frame"], c["source"]) == ("staged", 8, 0, "table")
     # precisions without a choice of products report their own count
     assert binding.get_config(300, 300, "fp16") == DEFAULT
     assert binding.get_config(100, 50, "bf16x4")["products"] == 4
@@ -88,7 +88,7 @@ def test_lookup_by_bucket(tmp_path):
     json.dumps(table([entry("split_bf16", 0, 0, products=5)])),                  # products
     json.dumps(table([entry("split_bf16", 3, 0)])),                              # bucket range
     json.dumps(table([entry("split_bf16", 0, 0, schedule="other")])),
-    json.dumps(table([entry("split_bf16", 0, 0, schedule="pingpong")])),
+    json.dumps(table([entry("split_bf16", 0, 0, schedule="looped")])),
     json.dumps(table([entry("split_bf16", 0, 0, band=0)])),
     json.dumps(table([entry("split_bf16", 0, 0, frame=2)])),
     json.dumps(table([entry("fp64", 0, 0)])),                                    # no tile kernel
@@ -151,7 +151,7 @@ def test_committed_table_covers_every_bucket():
         assert key in e["ms"]
         assert e["ms"][key] <= min(e["ms"].values()) * 1.0201
         c = binding.get_config(e["N"], e["L"], name[e["precision"]])
-        frame = e.get("frame", 1) if e["schedule"] != "persistent" else 0
+        frame = e.get("frame", 1) if e["schedule"] == "staged" else 0
         assert (c["products"], c["schedule"], c["band"], c["frame"], c["source"]) == \
             (e["products"], e["schedule"], e["band"], frame, "table")
     binding.load_tuning(None)
