@@ -5,14 +5,19 @@
 // the fix-up.  In the reference frame (see ModelSet) the model is first
 // superimposed onto the reference structure by its optimal rotation, the
 // operands are its residuals from the reference, and the per-model FP64
-// terms U = G + P and P^T are recorded for the epilogue.  One wave per
-// (padded) model over all model sets of a launch; HBM-bound (reads 12 L bytes
-// per model, plus the reference's 12 L from L2 in the frame; writes the
-// operands once).
+// terms U = G + P and P^T are recorded for the epilogue.  A group of
+// PREP_W lanes per (padded) model, 64 / PREP_W models per wave, over all
+// model sets of a launch: the per-model work (reductions, the rotation)
+// dominates at typical lengths, and a wave shares it over several models.
+// Reads 12 L bytes per model (twice: two passes, the second from L2), plus
+// the reference's 12 L from L2 in the frame; writes the operands once.
 #include "eq2.h"
 #include "internal.h"
 
 namespace clusco {
+
+constexpr int PREP_W = 8;
+static_assert(REF_CANDIDATES <= PREP_W, "a group holds every reference candidate");
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -34,13 +39,14 @@ __device__ __forceinline__ float bf16_bits_to_float(uint16_t b)
     return __uint_as_float((uint32_t)b << 16);
 }
 
-// Sums of N values over the wave, the N reductions interleaved (their
-// cross-lane steps overlap instead of queueing behind one another).
-template <int N>
+// Sums of N values over aligned groups of W lanes (W = 64: the wave), the N
+// reductions interleaved (their cross-lane steps overlap instead of queueing
+// behind one another).
+template <int W = 64, int N>
 __device__ __forceinline__ void wave_sums(double (&v)[N])
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = W / 2; o > 0; o >>= 1) {
         double t[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) t[k] = __shfl_xor(v[k], o, 64);
@@ -144,20 +150,22 @@ __global__ __launch_bounds__(256) void ref_moments_kernel(PrepLaunch a)
 
 // The chosen reference of a set: of the K candidates, the one whose squared
 // cRMSDs to the other K - 1 sum to the least (ties to the lowest index), so
-// that an outlier model is not the reference.  Every lane returns it.
-__device__ __forceinline__ int ref_choice(const double *info, int K, int lane)
+// that an outlier model is not the reference.  Lane `base + k` of a group
+// sums candidate k's row (k < K <= the group's width); every lane of the
+// group returns the choice.
+__device__ __forceinline__ int ref_choice(const double *info, int K, int sl, int base)
 {
     double sum = 0.0;
-    if (lane < K) {
+    if (sl < K) {
         int t = 0;
         for (int p = 0; p < REF_CANDIDATES; ++p)
             for (int q = p + 1; q < REF_CANDIDATES; ++q, ++t)
-                if (q < K && (p == lane || q == lane)) sum += info[t];
+                if (q < K && (p == sl || q == sl)) sum += info[t];
     }
     int best = 0;
-    double bsum = __shfl(sum, 0, 64);
+    double bsum = __shfl(sum, base, 64);
     for (int k = 1; k < K; ++k) {
-        const double v = __shfl(sum, k, 64);
+        const double v = __shfl(sum, base + k, 64);
         if (v < bsum) {
             bsum = v;
             best = k;
@@ -169,10 +177,13 @@ __device__ __forceinline__ int ref_choice(const double *info, int K, int lane)
 template <int MODE>
 __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 {
-    const int64_t g = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (g == 0 && lane < 4) a.counters[lane] = 0;
-    if (g == 0 && lane == 0 && a.zero64) *a.zero64 = 0ull;
+    // PREP_W lanes per model: a wave takes 64 / PREP_W consecutive models
+    const int sl = (int)threadIdx.x % PREP_W;
+    const int64_t g0 = (int64_t)blockIdx.x * (64 / PREP_W) + (int64_t)threadIdx.x / PREP_W;
+    const bool live = g0 < a.total;                // groups past the last model write nothing
+    const int64_t g = live ? g0 : a.total - 1;
+    if (blockIdx.x == 0 && threadIdx.x < 4) a.counters[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.zero64) *a.zero64 = 0ull;
 
     ModelSet s;
     if (a.table) {
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
     if (frame) {
         const double *info = (const double *)(a.ws + s.refinfo);
         const int K = (int)(s.ref_N < REF_CANDIDATES ? s.ref_N : REF_CANDIDATES);
-        const int k = ref_choice(info, K, lane);
+        const int k = ref_choice(info, K, sl, (int)threadIdx.x - sl);
         xr = (s.ref_b ? a.XB : a.XA) + s.ref_X + (int64_t)k * L * 3;
 #pragma unroll
         for (int t = 0; t < 3; ++t) cr[t] = info[RI_CEN + 3 * k + t];
@@ -213,7 +224,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 #pragma unroll
     for (int t = 0; t < 12; ++t) m1[t] = 0.0;
     if (real) {
-        for (int64_t l = lane; l < L; l += 64) {
+        for (int64_t l = sl; l < L; l += PREP_W) {
             double xv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -230,10 +241,10 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
                     for (int q = 0; q < 3; ++q) m1[3 + 3 * p + q] = fma(xv[p], rv[q], m1[3 + 3 * p + q]);
             }
         }
-        wave_sums(m1);
     }
+    wave_sums<PREP_W>(m1);
     const double c0 = m1[0] * inv, c1 = m1[1] * inv, c2 = m1[2] * inv;
-    if (lane == 0) {
+    if (sl == 0 && live) {
         cen[3 * m] = c0;
         cen[3 * m + 1] = c1;
         cen[3 * m + 2] = c2;
@@ -281,7 +292,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 #pragma unroll
     for (int t = 0; t < 12; ++t) m2[t] = 0.0;
     const int64_t Lend = MODE == MODE_FP64 ? L : s.Lp;
-    for (int64_t l = lane; l < Lend; l += 64) {
+    for (int64_t l = sl; l < Lend; l += PREP_W) {
         const bool in = real && l < L;
         double av[3], rv[3], dv[3], qv[3];
 #pragma unroll
@@ -303,7 +314,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
                 qv[c] = (double)f;
                 const int64_t kb = l >> 3, h = (l >> 2) & 1, el = l & 3;
                 const int64_t idx = (((R * KB + kb) * 3 + c) * 64 + r + 32 * h) * 4 + el;
-                ((float *)(a.ws + s.ops))[idx] = f;
+                if (live) ((float *)(a.ws + s.ops))[idx] = f;
             } else {
                 const int64_t kb = l >> 4, h = (l >> 3) & 1, el = l & 7;
                 const int64_t base = (((R * KB + kb) * 3 + c) * 2) * 64;
@@ -316,15 +327,19 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
                     hv = (double)bf16_bits_to_float(hb);
                     const uint16_t lb = bf16_bits_rn((float)(v - hv));
                     lv = (double)bf16_bits_to_float(lb);
-                    ops[hi_idx] = hb;
-                    ops[lo_idx] = lb;
+                    if (live) {
+                        ops[hi_idx] = hb;
+                        ops[lo_idx] = lb;
+                    }
                 } else {
                     const _Float16 hh = (_Float16)(float)v;
                     hv = (double)(float)hh;
                     const _Float16 ll = (_Float16)(float)(v - hv);
                     lv = (double)(float)ll;
-                    ops[hi_idx] = __builtin_bit_cast(uint16_t, hh);
-                    ops[lo_idx] = __builtin_bit_cast(uint16_t, ll);
+                    if (live) {
+                        ops[hi_idx] = __builtin_bit_cast(uint16_t, hh);
+                        ops[lo_idx] = __builtin_bit_cast(uint16_t, ll);
+                    }
                 }
                 qv[c] = hv + lv;   // exact in FP64
             }
@@ -338,8 +353,8 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
             for (int t = 0; t < 3; ++t) m2[3 + 3 * c + t] = fma(qv[c], rv[t], m2[3 + 3 * c + t]);
         }
     }
-    wave_sums(m2);
-    if (lane == 0) {
+    wave_sums<PREP_W>(m2);
+    if (sl == 0 && live) {
         E64[m] = m2[0];
         if (MODE == MODE_FP64) {
             E[m] = 0.0;
@@ -365,7 +380,7 @@ hipError_t launch_prep(const PrepLaunch &a, hipStream_t s)
     for (int k = 0; k < (a.table ? 0 : a.nset); ++k) frame |= a.set[k].frame != 0;
     if (frame && a.mode != MODE_FP64)
         ref_moments_kernel<<<dim3((unsigned)(a.nset * (REF_WAVES / 4))), dim3(256), 0, s>>>(a);
-    dim3 grid((unsigned)a.total), block(64);
+    dim3 grid((unsigned)((a.total + 64 / PREP_W - 1) / (64 / PREP_W))), block(64);
     switch (a.mode) {
     case MODE_FP32: prep_kernel<MODE_FP32><<<grid, block, 0, s>>>(a); break;
     case MODE_BF16: prep_kernel<MODE_BF16><<<grid, block, 0, s>>>(a); break;
