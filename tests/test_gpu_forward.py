@@ -167,3 +167,37 @@ def test_prealigned_near_identical(cl, prec):
     err = np.abs(got - want)
     say(f"  max err {err.max():.3e}")
     assert err.max() < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_packed_index_beyond_2_31(cl, prec):
+    """N = 66,000 models: the packed output (2.178e9 scores, 8.7 GB) runs past
+    2^31 elements, so every offset must be 64-bit.  Checked on the oracle's
+    pairs at the end of the triangle, around the 2^31 boundary and uniformly."""
+    N, L = 66000, 8
+    say(f"[parity] N={N} L={L} (packed index beyond 2^31), {prec}")
+    x = synth.make_ensemble(66, N, L, sigma=(0.5, 4.0))
+    rng = np.random.default_rng(66)
+    I, J = random_pairs(rng, N, 20000)
+    # the last rows of the triangle, and the row holding packed index 2^31
+    tail_i = np.r_[np.full(50, N - 2), np.arange(N - 60, N - 1)]
+    tail_j = np.r_[np.full(50, N - 1), np.full(59, N - 1)]
+    k31 = 2 ** 31
+    row = int(np.searchsorted(oracle.packed_index(np.arange(N - 1), np.arange(1, N), N), k31,
+                              side="right")) - 1
+    mid_j = np.arange(row + 1, N)                  # the whole row across 2^31
+    I = np.r_[I, tail_i, np.full(len(mid_j), row)]
+    J = np.r_[J, tail_j, mid_j]
+    assert oracle.packed_index(I, J, N).max() == N * (N - 1) // 2 - 1
+    assert (oracle.packed_index(I, J, N) >= k31).any() and (oracle.packed_index(I, J, N) < k31).any()
+    xd = torch.from_numpy(x).cuda()
+    out = cl.crmsd_matrix(xd, prec)
+    torch.cuda.synchronize()
+    assert out.numel() == N * (N - 1) // 2
+    got = out[torch.from_numpy(oracle.packed_index(I, J, N)).cuda()].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    want = oracle.crmsd_pairs(x, I, J)
+    err = np.abs(got.astype(np.float64) - want)
+    say(f"  {len(I)} pairs, max err {err.max():.3e}")
+    assert err.max() < TOL[prec]
