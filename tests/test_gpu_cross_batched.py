@@ -150,3 +150,32 @@ def test_batched_full_size_sampled(cl, full_batch, prec):
         worst = max(worst, err)
         assert err < tol, (e.shape, err)
     say(f"  max err {worst:.3e} A over {sum(len(s[0]) for s in samples)} pairs")
+
+
+def test_cross_index_beyond_2_31(cl):
+    """Na = Nb = 47,000: the dense output (2.209e9 scores) runs past 2^31
+    elements; sampled against the oracle, including the last row and the row
+    that crosses 2^31."""
+    Na = Nb = 47000
+    L = 4
+    say(f"[cross] Na={Na} Nb={Nb} L={L} (dense index beyond 2^31), bf16")
+    x = synth.make_ensemble(47, Na + Nb, L, sigma=(0.5, 4.0))
+    A, B = x[:Na], x[Na:]
+    rng = np.random.default_rng(47)
+    ia = rng.integers(0, Na, 20000)
+    ib = rng.integers(0, Nb, 20000)
+    row = (2 ** 31) // Nb
+    ia = np.r_[ia, np.full(Nb, row), np.full(500, Na - 1)]
+    ib = np.r_[ib, np.arange(Nb), np.arange(Nb - 500, Nb)]
+    k = ia.astype(np.int64) * Nb + ib
+    assert k.max() == Na * Nb - 1 and (k >= 2 ** 31).any() and (k < 2 ** 31).any()
+    out = cl.crmsd_cross(dev(A), dev(B), "bf16")
+    torch.cuda.synchronize()
+    assert out.shape == (Na, Nb)
+    got = out.reshape(-1)[torch.from_numpy(k).cuda()].cpu().numpy().astype(np.float64)
+    del out
+    torch.cuda.empty_cache()
+    want = oracle.crmsd_pairs(np.concatenate([A, B]), ia, Na + ib)
+    err = np.abs(got - want)
+    say(f"  {len(k)} pairs, max err {err.max():.3e}")
+    assert err.max() < TOL["bf16"]
