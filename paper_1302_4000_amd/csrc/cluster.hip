@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void km_stats(ClusterLaunch a)
     ss[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) {
+        if ((int)threadIdx.x < k) {
             sn[threadIdx.x] += sn[threadIdx.x + k];
             ss[threadIdx.x] += ss[threadIdx.x + k];
         }
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void km_pick(ClusterLaunch a)
     si[threadIdx.x] = bc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+        if ((int)threadIdx.x < s) {
             const int c2 = si[threadIdx.x + s];
             const double v2 = sv[threadIdx.x + s];
             if (c2 >= 0 && (si[threadIdx.x] < 0 || v2 < sv[threadIdx.x] ||
