@@ -155,3 +155,30 @@ def test_committed_table_covers_every_bucket():
         assert (c["products"], c["schedule"], c["band"], c["frame"], c["source"]) == \
             (e["products"], e["schedule"], e["band"], frame, "table")
     binding.load_tuning(None)
+
+
+def test_parser_survives_arbitrary_text(tmp_path):
+    """Random and truncated inputs: the parser rejects or accepts them but
+    never crashes, and a rejected file leaves the loaded table unchanged."""
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+    good = json.dumps(table([entry("split_bf16", 0, 0, 4, "persistent", 8)]))
+    binding.load_tuning(write(tmp_path, good, "good.json"))
+    before = binding.get_config(100, 50, "bf16")
+    path = tmp_path / "fuzz.json"
+
+    @hyp.settings(max_examples=300, deadline=None, derandomize=True)
+    @hyp.given(st.one_of(st.text(max_size=200),
+                         st.integers(0, len(good)).map(lambda n: good[:n]),
+                         st.lists(st.sampled_from(list('{}[]",:0123456789.-e truefalsnul')),
+                                  max_size=120).map("".join)))
+    def check(text):
+        path.write_text(text)
+        try:
+            binding.load_tuning(str(path))
+        except binding.ClucsoError:
+            assert binding.get_config(100, 50, "bf16") == before
+            return
+        binding.load_tuning(write(tmp_path, good, "good.json"))   # accepted: restore
+
+    check()
