@@ -221,11 +221,26 @@ __global__ __launch_bounds__(256) void km_update(ClusterLaunch a)
     const int c = blockIdx.x;
     long long key = 0;
     int64_t idx = -1;
-    for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x)
-        if (a.label[i] == c && (idx < 0 || a.cost[i] < key)) {   // ascending i: ties keep the first
-            key = a.cost[i];
-            idx = i;
+    // eight models per thread and round, their loads independent of the
+    // comparisons (a scan with one dependent load pair per model waited on
+    // every one); ascending i within a thread: ties keep the first
+    constexpr int U = 8;
+    for (int64_t i0 = threadIdx.x; i0 < a.N; i0 += U * (int64_t)blockDim.x) {
+        int lab[U];
+        long long cost[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * (int64_t)blockDim.x;
+            lab[u] = i < a.N ? a.label[i] : -1;
+            cost[u] = i < a.N ? a.cost[i] : 0;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (lab[u] == c && (idx < 0 || cost[u] < key)) {
+                key = cost[u];
+                idx = i0 + u * (int64_t)blockDim.x;
+            }
+    }
     block_min(key, idx);
     if (threadIdx.x == 0) {
         if (idx >= 0 && idx != a.medoid[c]) {
