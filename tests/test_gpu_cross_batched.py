@@ -179,3 +179,46 @@ def test_cross_index_beyond_2_31(cl):
     err = np.abs(got - want)
     say(f"  {len(k)} pairs, max err {err.max():.3e}")
     assert err.max() < TOL["bf16"]
+
+
+def test_batched_under_the_callers_graph_capture(cl):
+    """A batched call captured into the caller's own graph (after one eager
+    call with the same shapes, which caches the plan) replays to the eager
+    result, with unrelated eager work between the replays; a shape signature
+    with no cached plan is refused under capture (nothing is enqueued)."""
+    say("[batched] caller's graph capture")
+    ens = small_batch()
+    b = cl.Batch([e.shape[:2] for e in ens])
+    flat = b.pack([torch.from_numpy(e) for e in ens], "cuda")
+    ws = torch.empty(cl.batched_workspace_size(b, "bf16"), dtype=torch.uint8, device="cuda")
+    out = torch.empty(b.n_out, dtype=torch.float32, device="cuda")
+    ref = cl.crmsd_batched(b, flat, "bf16", out=out, ws=ws).clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cl.crmsd_batched(b, flat, "bf16", out=out, ws=ws)
+    x0 = dev(ens[0])
+    for rep in range(4):
+        out.fill_(-1.0)
+        cl.crmsd_matrix(x0, "fp32")                  # other work on the same device
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+    # new shapes, never planned: refused under capture
+    ens2 = [synth.make_ensemble(91, 41, 19), synth.make_ensemble(92, 37, 23)]
+    b2 = cl.Batch([e.shape[:2] for e in ens2])
+    flat2 = b2.pack([torch.from_numpy(e) for e in ens2], "cuda")
+    ws2 = torch.empty(cl.batched_workspace_size(b2, "bf16"), dtype=torch.uint8, device="cuda")
+    out2 = torch.empty(b2.n_out, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    g2 = torch.cuda.CUDAGraph()
+    with pytest.raises(cl.binding.ClucsoError):
+        with torch.cuda.graph(g2):
+            cl.crmsd_batched(b2, flat2, "bf16", out=out2, ws=ws2)
+    torch.cuda.synchronize()
+    # and works eagerly afterwards
+    got = cl.crmsd_batched(b2, flat2, "bf16", out=out2, ws=ws2)
+    torch.cuda.synchronize()
+    for e, part in zip(ens2, b2.split(got)):
+        assert np.abs(part.cpu().numpy().astype(np.float64) - oracle.crmsd_matrix(e)).max() < TOL["bf16"]
