@@ -595,44 +595,76 @@ struct StageGeom {
     static constexpr int PER = SLOT / 256;              // u32x4 loads per thread
 };
 
-// Thread tid's PER chunks (u32x4) of K-block kb of the tile whose first row
-// blocks of A and B are rA and rB (row block R, K-block kb: chunk base
-// (R*KB + kb)*REGION), sent straight from global memory to the LDS slot
-// (global_load_lds_dwordx4, no registers): load m of wave w moves 64
-// consecutive chunks, lane l's 16 bytes landing at slot + 256 m + 64 w + l.
-// The wave's 64 chunks always lie in one region (REGION is a multiple of 64).
-// kb < 0 issues the same number of loads, so that every step has the same
-// count in flight: with kb = STAGE_FRAME, into chunks 0 .. 2 FRAME_CHUNKS - 1,
-// the reference-frame terms of the tile (U of its 64 rows, then P^T of its 64
-// columns, 9 doubles per model, contiguous in the workspace), the rest from
-// the first chunks of A (always present, cached) like every other kb < 0;
-// nothing reads a slot filled with the latter again.
+// K-block kb (>= 0) of the tile whose first row blocks of A and B are rA
+// and rB, sent straight from global memory to the LDS slot (no registers):
+// wave w moves region w (row block rA + w of A for w < 2, rB + w - 2 of B
+// otherwise; region R of K-block kb is chunks (R*KB + kb)*REGION onwards),
+// load m carrying its chunks 64 m .. 64 m + 63, lane l's 16 bytes landing at
+// slot + REGION w + 64 m + l.  The region's start is wave-uniform (kept in
+// scalar registers, stage_base) and the lane's byte offset fixed, so a load
+// needs no vector address arithmetic.
+//
+// kb < 0 issues the same number of loads into the same chunks, so that every
+// step has the same count in flight: with kb = STAGE_FRAME, into chunks
+// 0 .. 2 FRAME_CHUNKS - 1, the reference-frame terms of the tile (U of its 64
+// rows, then P^T of its 64 columns, 9 doubles per model, contiguous in the
+// workspace), the rest from the first chunks of A (always present, cached)
+// like every other kb < 0; nothing reads a slot filled with the latter again.
 constexpr int64_t STAGE_PAST = -1, STAGE_FRAME = -2;
 constexpr int FRAME_CHUNKS = 2 * ROWBLK * 9 * 8 / 16;   // 16-byte chunks per 64 models
 
+// Start of wave w's region in K-block 0 of the tile (wave-uniform).
+template <int MODE>
+__device__ __forceinline__ const char *stage_base(const Problem &p, const char *ws, int64_t rA,
+                                                  int64_t rB, int w)
+{
+    using G = StageGeom<MODE>;
+    const int64_t span = p.KB * G::REGION;           // chunks of one row block
+    const u32x4 *src = w < 2 ? (const u32x4 *)(ws + p.opsA) + (rA + w) * span
+                             : (const u32x4 *)(ws + p.opsB) + (rB + w - 2) * span;
+    const uint64_t v = (uint64_t)src;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const char *)(((uint64_t)hi << 32) | lo);
+}
+
 template <int MODE>
 __device__ __forceinline__ void stage_dma(const Problem &p, const char *ws, int64_t rA,
-                                          int64_t rB, int64_t kb, int tid, int w, u32x4 *slot)
+                                          int64_t rB, int64_t kb, int tid, int w,
+                                          const char *base, u32x4 *slot)
 {
     using G = StageGeom<MODE>;
     static_assert(2 * FRAME_CHUNKS <= G::SLOT, "frame terms fit a slot");
-    const int64_t KB = p.KB;
-    const bool live = kb >= 0;
+    static_assert(G::PER * 64 == G::REGION, "one region per wave");
+    if (kb >= 0) {
+        // The wave-uniform start of each load's chunks is held opaque in
+        // scalar registers and the lane's 32-bit byte offset opaque in a
+        // vector register, so that every address stays scalar base + 32-bit
+        // offset (no 64-bit vector address arithmetic per load).
+        uint32_t vo = (uint32_t)(tid & 63) * 16u;
+        asm volatile("" : "+v"(vo));
+#pragma unroll
+        for (int m = 0; m < G::PER; ++m) {
+            const char *row = base + (kb * G::REGION + 64 * m) * 16;
+            asm volatile("" : "+s"(row));
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(row + vo),
+                                             (void __attribute__((address_space(3))) *)(slot + G::REGION * w + 64 * m),
+                                             16, 0, 0);
+        }
+        return;
+    }
+    // once or twice per tile: chunk q of the slot from the frame terms or A
     const u32x4 *ops = (const u32x4 *)(ws + p.opsA);
-    const u32x4 *rowA = ops + (rA * KB + (live ? kb : 0)) * G::REGION;
-    const u32x4 *rowB = (const u32x4 *)(ws + p.opsB) + (rB * KB + (live ? kb : 0)) * G::REGION;
-    const int64_t next = KB * G::REGION;            // the next row block, same K-block
     const u32x4 *fU = (const u32x4 *)(ws + p.UA) + rA * (ROWBLK * 9 * 8 / 16);
     const u32x4 *fP = (const u32x4 *)(ws + p.PTB) + rB * (ROWBLK * 9 * 8 / 16);
 #pragma unroll
     for (int m = 0; m < G::PER; ++m) {
-        const int q = tid + 256 * m;
-        const int region = q / G::REGION, off = q % G::REGION;
-        const u32x4 *src = live ? (region < 2 ? rowA : rowB) + (region & 1) * next + off : ops + off;
+        const int q = G::REGION * w + 64 * m + (tid & 63);
+        const u32x4 *src = ops + q;
         if (kb == STAGE_FRAME && q < 2 * FRAME_CHUNKS)
             src = q < FRAME_CHUNKS ? fU + q : fP + (q - FRAME_CHUNKS);
         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
-                                         (void __attribute__((address_space(3))) *)(slot + 256 * m + 64 * w),
+                                         (void __attribute__((address_space(3))) *)(slot + G::REGION * w + 64 * m),
                                          16, 0, 0);
     }
 }
@@ -685,8 +717,9 @@ __device__ __forceinline__ void staged_tile(const TileLaunch &a, int64_t t, int 
     // usually in its FP64 epilogue, and the MFMA issue should not wait behind
     // that stream of VALU instructions
     __builtin_amdgcn_s_setprio(3);
-    stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 0, tid, w, slot0);
-    stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, KB > 1 ? 1 : kb_frame, tid, w, slot1);
+    const char *const rbase = stage_base<MODE>(p, a.ws, 2 * bi, 2 * bj, w);
+    stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, 0, tid, w, rbase, slot0);
+    stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj, KB > 1 ? 1 : kb_frame, tid, w, rbase, slot1);
     wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
 
@@ -703,7 +736,8 @@ __device__ __forceinline__ void staged_tile(const TileLaunch &a, int64_t t, int 
     // loads, and the LDS reads are complete once their MFMAs have issued.
     auto step = [&](int64_t kb, const u32x4 *cur, u32x4 *nxt) {
         stage_dma<MODE>(p, a.ws, 2 * bi, 2 * bj,
-                        kb + 2 < KB ? kb + 2 : (kb + 2 == KB ? kb_frame : STAGE_PAST), tid, w, nxt);
+                        kb + 2 < KB ? kb + 2 : (kb + 2 == KB ? kb_frame : STAGE_PAST), tid, w, rbase,
+                        nxt);
         pin_order();
         const u32x4 *sA = cur + wy * G::REGION + lane;
         const u32x4 *sB = cur + (2 + wx) * G::REGION + lane;
