@@ -121,19 +121,19 @@ __device__ __forceinline__ double eq2_lrmsd2(const double h[9], double EA, doubl
     return fma(-2.0, eq2_signed_sum(h), EA + EB);
 }
 
-// L * cRMSD^2 of NP independent pairs at once, for the tile epilogue: the
-// arithmetic of eq2_lrmsd2 written with the fewest instructions.  The NP
-// dependency chains sit side by side.  Instead of branches and selects on
-// degenerate inputs, three floors keep every operation finite: the slope in
-// the Newton step (at least 1e-30 c2^2, so a step at an exact double root is
-// 0/tiny = 0), the root (at least max(c2, 1e-300)/3, so 1/sqrt never sees 0)
-// and (s2 + S s3)^2 (at least 1e-300).  For H = 0 the sum then comes out as
-// about 1e-150 instead of 0, far below the score's resolution.
+// State between the two stages of eq2_lrmsd2_batch (per pair: the largest
+// root l1, the coefficient c2, det H and the floored c2).
+template <int NP>
+struct Eq2Roots {
+    double l[NP], c2[NP], det[NP], c2f[NP];
+};
+
+// First stage: coefficients and the largest root of every pair.
 template <int NP, int STEPS>
-__device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const double (&ea)[NP],
-                                                 const double (&eb)[NP], double (&out)[NP])
+__device__ __forceinline__ void eq2_roots_batch(const double (&h)[NP][9], Eq2Roots<NP> &st)
 {
-    double c2[NP], c1[NP], c0[NP], det[NP], l[NP], step[NP], c2f[NP], floor_fp[NP];
+    double c1[NP], c0[NP], step[NP], floor_fp[NP];
+    double (&c2)[NP] = st.c2, (&det)[NP] = st.det, (&l)[NP] = st.l, (&c2f)[NP] = st.c2f;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const Eq2Coef c = eq2_coefficients(h[p]);
@@ -173,20 +173,44 @@ __device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const
             } while (++it < 60 && fabs(step[p]) > 1e-15 * l[p]);
         }
     }
-    // The hardware reciprocal square roots (relative error below 6e-8 on
-    // gfx950) get one Newton step each: an error of that size in the sum
-    // s1 + s2 + S s3, whose magnitude is the radii E, would dominate the
-    // contraction error of the reference frame (proportional to the residual
-    // radii only).
+}
+
+// Second stage: s1 + s2 + S s3 from the root, and L cRMSD^2.
+// The hardware reciprocal square roots (relative error below 6e-8 on
+// gfx950) get one Newton step each: an error of that size in the sum
+// s1 + s2 + S s3, whose magnitude is the radii E, would dominate the
+// contraction error of the reference frame (proportional to the residual
+// radii only).
+template <int NP>
+__device__ __forceinline__ void eq2_finish_batch(const Eq2Roots<NP> &st, const double (&ea)[NP],
+                                                 const double (&eb)[NP], double (&out)[NP])
+{
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const double l1 = fmax(l[p], c2f[p] * (1.0 / 3.0));
+        const double l1 = fmax(st.l[p], st.c2f[p] * (1.0 / 3.0));
         const double r1 = rsqrt_refined(l1);
-        const double t = fma(2.0 * det[p], r1, c2[p] - l1);        // (s2 + S s3)^2
+        const double t = fma(2.0 * st.det[p], r1, st.c2[p] - l1);   // (s2 + S s3)^2
         const double tp = fmax(t, 1e-300);
-        const double sum = fma(l1, r1, tp * rsqrt_refined(tp));   // s1 + s2 + S s3
+        const double sum = fma(l1, r1, tp * rsqrt_refined(tp));    // s1 + s2 + S s3
         out[p] = fma(-2.0, sum, ea[p] + eb[p]);
     }
+}
+
+// L * cRMSD^2 of NP independent pairs at once, for the tile epilogue: the
+// arithmetic of eq2_lrmsd2 written with the fewest instructions.  The NP
+// dependency chains sit side by side.  Instead of branches and selects on
+// degenerate inputs, three floors keep every operation finite: the slope in
+// the Newton step (at least 1e-30 c2^2, so a step at an exact double root is
+// 0/tiny = 0), the root (at least max(c2, 1e-300)/3, so 1/sqrt never sees 0)
+// and (s2 + S s3)^2 (at least 1e-300).  For H = 0 the sum then comes out as
+// about 1e-150 instead of 0, far below the score's resolution.
+template <int NP, int STEPS>
+__device__ __forceinline__ void eq2_lrmsd2_batch(const double (&h)[NP][9], const double (&ea)[NP],
+                                                 const double (&eb)[NP], double (&out)[NP])
+{
+    Eq2Roots<NP> st;
+    eq2_roots_batch<NP, STEPS>(h, st);
+    eq2_finish_batch<NP>(st, ea, eb, out);
 }
 
 // ------------------------------------------------------------ backward

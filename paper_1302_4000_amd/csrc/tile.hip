@@ -156,13 +156,9 @@ __device__ __forceinline__ void contract(const char *opsA, const char *opsB, int
     }
 }
 
-// Forward epilogue: EPI_NP pairs evaluated side by side (one measured
-// fastest: a wave's FP64 issue rate, not its dependency chains, is the
-// limit) and EPI_STEPS Newton steps on the largest root before the
-// rare-lane continuation of eq2_largest_root.
-#ifndef EPI_NP
-#define EPI_NP 1
-#endif
+// Forward epilogue: one pair at a time per lane (two or four side by side
+// measured no faster) and EPI_STEPS Newton steps on the largest root before
+// the rare-lane continuation of eq2_largest_root.
 #ifndef EPI_STEPS
 #define EPI_STEPS 3
 #endif
@@ -256,6 +252,37 @@ __device__ __forceinline__ void pair_h(const f32x16 acc[9], int r, const double 
     }
 }
 
+// The column's frame terms (P^T of column j = lane%32), read once and held
+// in registers for the block's sixteen pairs (the empty asm stops the
+// compiler from re-reading them per pair).
+template <bool FRAME>
+__device__ __forceinline__ void col_terms(const double *pcol, int lane, double (&pc)[9])
+{
+#pragma unroll
+    for (int u = 0; u < 9; ++u) pc[u] = FRAME ? pcol[9 * (lane & 31) + u] : 0.0;
+    if constexpr (FRAME) {
+#pragma unroll
+        for (int u = 0; u < 9; ++u) asm volatile("" : "+v"(pc[u]));
+    }
+}
+
+// Row terms of the pair in accumulator slot k (row 8(k/4) + 4(lane/32) +
+// k%4 of the block): U from LDS, E and F from the lane that loaded them.
+// The epilogues request them one pair ahead, between the current pair's
+// root and its square roots, so that their LDS latency is hidden.
+template <bool FRAME>
+__device__ __forceinline__ void row_terms(const double *urow, const EpiRadii &er, int lane, int k,
+                                          double (&u)[9], double &e, float &f)
+{
+    const int rr = 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3);
+    if constexpr (FRAME) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) u[t] = urow[9 * rr + t];
+    }
+    e = row_radius(er, rr);
+    f = row_flag(er, rr);
+}
+
 // Where the epilogue finds the reference-frame terms of its wave's block: U
 // of its 32 rows and P^T of its 32 columns, 9 doubles per model (in LDS for
 // the staged kernel, in the workspace for the persistent one).
@@ -283,45 +310,44 @@ __device__ __forceinline__ void epilogue_t(const TileLaunch &a, const Problem &p
     const double Ej = er.ej;
     const float Fj = er.fj;
     const bool jlive = j < (SYM ? NA : NB);
-    const double *pcol = ft.pcol + 9 * (lane & 31);
+    double pc[9];
+    col_terms<FRAME>(ft.pcol, lane, pc);
+    double ur[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ei;
+    float fi;
+    row_terms<FRAME>(ft.urow, er, lane, 0, ur, ei, fi);
     // the flag is folded in pair by pair into a wave-wide mask (scalar ALU):
     // the empty asm keeps the compiler from deferring all sixteen comparisons
     // to the end of the block, which would hold every score and row weight in
     // registers until then
     uint64_t flagged = 0;
+    int64_t base = 0;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int64_t i0 = job.Ra * ROWBLK + 8 * g + 4 * (lane >> 5);
+    for (int k = 0; k < 16; ++k) {
+        const int64_t i = job.Ra * ROWBLK + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3);
         // row base k(i, j) - j: packed rows advance by N - i - 2, dense by NB
-        int64_t base = SYM ? i0 * (2 * NA - i0 - 1) / 2 - i0 - 1 : i0 * NB;
-#pragma unroll
-        for (int q0 = 0; q0 < 4; q0 += EPI_NP) {
-            double h[EPI_NP][9], ei[EPI_NP], ej[EPI_NP], lr2[EPI_NP];
-#pragma unroll
-            for (int b = 0; b < EPI_NP; ++b) {
-                const int rr = 8 * g + 4 * (lane >> 5) + q0 + b;
-                pair_h<FRAME>(acc, 4 * g + q0 + b, ft.urow + 9 * rr, pcol, h[b]);
-                ei[b] = row_radius(er, rr);
-                ej[b] = Ej;
-            }
-            eq2_lrmsd2_batch<EPI_NP, EPI_STEPS>(h, ei, ej, lr2);
-#pragma unroll
-            for (int b = 0; b < EPI_NP; ++b) {
-                const int64_t i = i0 + q0 + b;
-                // hardware square root (within 1 ulp): the score's tolerance is
-                // orders of magnitude above float rounding
-                const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[b] * invL, 0.0));
-                const bool live = jlive && (SYM ? i < j : i < NA);
-                if (live) out[base + j] = v;
-                const float fi = row_flag(er, 8 * g + 4 * (lane >> 5) + q0 + b);
-                flagged |= __ballot(fix && live && flag_pair(v, fi, Fj));
-                asm volatile("" : "+s"(flagged));
-                // the next row's base, kept incremental (the empty asm stops
-                // the compiler from re-deriving it with a multiplication)
-                base += SYM ? NA - i - 2 : NB;
-                asm volatile("" : "+v"(base));
-            }
+        if ((k & 3) == 0) base = SYM ? i * (2 * NA - i - 1) / 2 - i - 1 : i * NB;
+        double h[1][9], eiv[1] = {ei}, ejv[1] = {Ej}, lr2[1];
+        const float fcur = fi;
+        pair_h<FRAME>(acc, k, ur, pc, h[0]);
+        Eq2Roots<1> st;
+        eq2_roots_batch<1, EPI_STEPS>(h, st);
+        if (k + 1 < 16) {
+            __builtin_amdgcn_sched_barrier(0);
+            row_terms<FRAME>(ft.urow, er, lane, k + 1, ur, ei, fi);
+            __builtin_amdgcn_sched_barrier(0);
         }
+        eq2_finish_batch<1>(st, eiv, ejv, lr2);
+        // hardware square root (within 1 ulp): the score's tolerance is
+        // orders of magnitude above float rounding
+        const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[0] * invL, 0.0));
+        const bool live = jlive && (SYM ? i < j : i < NA);
+        if (live) out[base + j] = v;
+        flagged |= __ballot(fix && live && flag_pair(v, fcur, Fj));
+        asm volatile("" : "+s"(flagged));
+        // the next row's base, kept incremental (the empty asm stops the
+        // compiler from re-deriving it with a multiplication)
+        base += SYM ? NA - i - 2 : NB;
+        asm volatile("" : "+v"(base));
     }
     if (flagged != 0 && lane == 0) {
         const int s = atomicAdd(&a.counters[0], 1);
@@ -419,18 +445,18 @@ __device__ __forceinline__ void thr_scores_t(const TileLaunch &a, const Problem 
     const double Ej = er.ej;
     const float Fj = er.fj;
     const bool jlive = j < NA;
+    // Column and row terms are read from LDS per pair: the sixteen scores
+    // are held to the end here, and neither the column terms held in
+    // registers nor a row-term prefetch fit beside them without spills.
     const double *pcol = ft.pcol + 9 * (lane & 31);
     uint32_t emit = 0, flag = 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t i = job.Ra * ROWBLK + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int rr = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        double h[1][9], ei[1], ej[1], lr2[1];
+        double h[1][9], eiv[1] = {row_radius(er, rr)}, ejv[1] = {Ej}, lr2[1];
         pair_h<FRAME>(acc, r, ft.urow + 9 * rr, pcol, h[0]);
-        const double Ei = row_radius(er, rr);
-        ei[0] = Ei;
-        ej[0] = Ej;
-        eq2_lrmsd2_batch<1, EPI_STEPS>(h, ei, ej, lr2);   // the forward's arithmetic
+        eq2_lrmsd2_batch<1, EPI_STEPS>(h, eiv, ejv, lr2);   // the forward's arithmetic
         const float v = __builtin_amdgcn_sqrtf((float)fmax(lr2[0] * invL, 0.0));
         const bool live = jlive && i < j;
         const bool fl = fix && live && flag_pair(v, row_flag(er, rr), Fj);
