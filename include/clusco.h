@@ -125,7 +125,8 @@ clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L
  *             Backward and threshold calls always use the staged schedule; a
  *             batched call uses the one most of its work prefers, the
  *             persistent one only when no ensemble of the batch uses the frame
- *             (so each ensemble's scores equal those of its single call).
+ *             (so each ensemble's scores equal those of a single call with
+ *             the configuration the batch gives it, clusco_get_config_batched).
  *   band      tile rows per band of the tile order (L2 reuse of operands).
  *   frame     1: every model is first superimposed onto a reference structure
  *             (of the ensemble's first eight models, of set A's in a cross
@@ -151,8 +152,12 @@ clusco_status clusco_flag_epsilon(clusco_handle h, clusco_precision p, int64_t L
  *   "entries": [{"precision": "fp32" | "split_bf16" | "split_fp16" |
  *   "split_bf16x4", "n_bucket": i, "l_bucket": j, "products": 3 | 4,
  *   "schedule": "staged" | "persistent", "band": 1..256, optionally
- *   "frame": 0 | 1 (default 1), ...}]
- * (other keys are ignored). */
+ *   "frame": 0 | 1 (default 1) and "call": "single" | "batched" (default
+ *   "single"), ...}]
+ * (other keys are ignored).  A "batched" entry is what an ensemble of its
+ * bucket takes inside a batched call, where the per-call costs (the reference
+ * pass, launches) are shared by all ensembles and the best choice can differ
+ * from a single call's; a bucket without one uses its single-call entry. */
 #define CLUSCO_SCHED_STAGED 0
 #define CLUSCO_SCHED_PERSISTENT 1
 
@@ -175,6 +180,11 @@ const char *clusco_tuning_path(clusco_handle h);
 /* The configuration calls with these sizes and precision will use. */
 clusco_status clusco_get_config(clusco_handle h, int64_t N, int64_t L, clusco_precision p,
                                 clusco_config *cfg);
+/* The configuration an ensemble of these sizes takes inside a batched call
+ * (clusco_crmsd_batched): the bucket's "batched" entry when the table has
+ * one, else the same as clusco_get_config.  Host only; no device work. */
+clusco_status clusco_get_config_batched(clusco_handle h, int64_t N, int64_t L,
+                                        clusco_precision p, clusco_config *cfg);
 /* Use `cfg` (products, schedule, band) for every later call on this handle,
  * whatever the table says; NULL returns to the table.  For measurement (the
  * tuner times each candidate this way). */
@@ -268,7 +278,8 @@ size_t clusco_crmsd_batched_workspace_size(clusco_handle h, int32_t E, const int
  * cached by an earlier call with the same shapes (else
  * CLUSCO_ERR_UNSUPPORTED), and such a plan stays alive until clusco_destroy
  * because the caller's graph holds its device table.  Ensembles may not
- * overlap in out. */
+ * overlap in out.  Each ensemble takes its configuration from
+ * clusco_get_config_batched. */
 clusco_status clusco_crmsd_batched(clusco_handle h, int32_t E, const int64_t *h_N,
                                    const int64_t *h_L, const int64_t *h_coord_off,
                                    const int64_t *h_out_off, const float *coords,

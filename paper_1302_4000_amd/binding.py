@@ -78,6 +78,7 @@ def lib():
             "clusco_load_tuning": (st, [vp, ctypes.c_char_p]),
             "clusco_tuning_path": (ctypes.c_char_p, [vp]),
             "clusco_get_config": (st, [vp, i64, i64, st, ctypes.POINTER(Config)]),
+            "clusco_get_config_batched": (st, [vp, i64, i64, st, ctypes.POINTER(Config)]),
             "clusco_force_config": (st, [vp, ctypes.POINTER(Config)]),
             "clusco_drmsd_workspace_size": (sz, [vp, i64, i64, st]),
             "clusco_cluster_workspace_size": (sz, [vp, i64, i32]),
@@ -187,12 +188,13 @@ def tuning_path(device: int = 0) -> str:
     return lib().clusco_tuning_path(handle(device)).decode()
 
 
-def get_config(N: int, L: int, precision="bf16", device: int = 0) -> dict:
-    """The kernel configuration calls with these sizes will use."""
+def get_config(N: int, L: int, precision="bf16", device: int = 0, batched: bool = False) -> dict:
+    """The kernel configuration calls with these sizes will use (batched: the
+    one an ensemble of these sizes takes inside a batched call)."""
     h = handle(device)
     c = Config()
-    _check(lib().clusco_get_config(h, int(N), int(L), _prec(precision), ctypes.byref(c)), h,
-           "clusco_get_config")
+    name = "clusco_get_config_batched" if batched else "clusco_get_config"
+    _check(getattr(lib(), name)(h, int(N), int(L), _prec(precision), ctypes.byref(c)), h, name)
     return c.as_dict()
 
 

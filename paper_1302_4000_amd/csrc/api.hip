@@ -55,6 +55,7 @@ struct KernelCfg {
 
 struct TuneEntry {
     int mode, nb, lb;
+    int call;       // 0: single calls; 1: ensembles inside batched calls
     KernelCfg cfg;
 };
 
@@ -259,8 +260,10 @@ int bucket_of(const std::vector<int64_t> &edges, int64_t x)
 }
 
 // Configuration for a problem of N models (an all-vs-all ensemble, or the
-// all-vs-all size with as many pairs for a cross comparison) of L atoms.
-KernelCfg config_for(clusco_handle h, int mode, int64_t N, int64_t L)
+// all-vs-all size with as many pairs for a cross comparison) of L atoms; in a
+// batched call (batched) the bucket's batched entry when the table has one,
+// else its single-call entry.
+KernelCfg config_for(clusco_handle h, int mode, int64_t N, int64_t L, bool batched = false)
 {
     KernelCfg c;
     if (h->forced) {
@@ -268,13 +271,21 @@ KernelCfg config_for(clusco_handle h, int mode, int64_t N, int64_t L)
         c.source = 2;
     } else if (!h->tune.n_edges.empty() && !h->tune.l_edges.empty()) {
         const int nb = bucket_of(h->tune.n_edges, N), lb = bucket_of(h->tune.l_edges, L);
+        const int want = batched ? 1 : 0;
+        const TuneEntry *own = nullptr, *single = nullptr;
         for (const TuneEntry &t : h->tune.entries) {
-            if (t.mode == mode && t.nb == nb && t.lb == lb) {
-                c = t.cfg;
-                c.id = nb * (int)h->tune.l_edges.size() + lb;
-                c.source = 1;
+            if (t.mode != mode || t.nb != nb || t.lb != lb) continue;
+            if (t.call == want) {
+                own = &t;
                 break;
             }
+            if (t.call == 0 && !single) single = &t;
+        }
+        const TuneEntry *hit = own ? own : single;
+        if (hit) {
+            c = hit->cfg;
+            c.id = nb * (int)h->tune.l_edges.size() + lb;
+            c.source = 1;
         }
     }
     if (mode != MODE_BF16) c.products = mode == MODE_BF16X4 ? 4 : 3;
@@ -504,15 +515,19 @@ clusco_status parse_tuning(const std::string &text, const std::string &arch, Tun
             t.cfg.band = (int)bd->num;
             const JVal *fr = e.get("frame");
             if (fr) t.cfg.frame = fr->kind == JVal::NUM && (fr->num == 0 || fr->num == 1) ? (int)fr->num : -1;
-            ok = t.cfg.frame >= 0 && t.mode >= 0 && nb->num == t.nb && lb->num == t.lb && t.nb >= 0 &&
+            const JVal *cl = e.get("call");
+            t.call = 0;
+            if (cl) t.call = cl->kind == JVal::STR && cl->str == "single" ? 0
+                           : cl->kind == JVal::STR && cl->str == "batched" ? 1 : -1;
+            ok = t.call >= 0 && t.cfg.frame >= 0 && t.mode >= 0 && nb->num == t.nb && lb->num == t.lb && t.nb >= 0 &&
                  t.nb < (int)out.n_edges.size() && t.lb >= 0 && t.lb < (int)out.l_edges.size() &&
                  (t.cfg.products == 3 || t.cfg.products == 4) && t.cfg.schedule >= 0 &&
                  bd->num == t.cfg.band && t.cfg.band >= 1 && t.cfg.band <= 256;
         }
         if (!ok) {
             *err = "tuning file: bad entry (needs precision, n_bucket, l_bucket, products 3|4, "
-                   "schedule staged|persistent, band 1..256, optional frame 0|1, buckets "
-                   "within the edges)";
+                   "schedule staged|persistent, band 1..256, optional frame 0|1, optional call "
+                   "single|batched, buckets within the edges)";
             return CLUSCO_ERR_INVALID_ARG;
         }
         out.entries.push_back(t);
@@ -919,7 +934,7 @@ size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<M
     bool framed = false;
     for (int32_t e = 0; e < b.E; ++e) {
         if (b.N[e] < 2) continue;
-        cfg[e] = config_for(h, mode, b.N[e], b.L[e]);
+        cfg[e] = config_for(h, mode, b.N[e], b.L[e], true);
         framed = framed || cfg[e].frame;
         const int64_t nb = round_up(b.N[e], TILE) / TILE;
         vote[cfg[e].schedule] += (double)tri_count(nb) *
@@ -1118,13 +1133,13 @@ clusco_status clusco_load_tuning(clusco_handle h, const char *path)
     return st == CLUSCO_OK ? st : fail(h, st, err.c_str());
 }
 
-clusco_status clusco_get_config(clusco_handle h, int64_t N, int64_t L, clusco_precision p,
-                                clusco_config *cfg)
+static clusco_status get_config(clusco_handle h, int64_t N, int64_t L, clusco_precision p,
+                                clusco_config *cfg, bool batched)
 {
     if (!h || !cfg) return CLUSCO_ERR_INVALID_ARG;
     if (!valid_precision(p)) return fail(h, CLUSCO_ERR_UNSUPPORTED, "unknown precision");
     if (N < 0 || L < 1) return fail(h, CLUSCO_ERR_INVALID_ARG, "need N >= 0 and L >= 1");
-    const KernelCfg c = config_for(h, mode_of(p), N, L);
+    const KernelCfg c = config_for(h, mode_of(p), N, L, batched);
     cfg->products = c.products;
     cfg->schedule = c.schedule;
     cfg->band = c.band;
@@ -1132,6 +1147,18 @@ clusco_status clusco_get_config(clusco_handle h, int64_t N, int64_t L, clusco_pr
     cfg->source = c.source;
     cfg->bucket = c.id;
     return CLUSCO_OK;
+}
+
+clusco_status clusco_get_config(clusco_handle h, int64_t N, int64_t L, clusco_precision p,
+                                clusco_config *cfg)
+{
+    return get_config(h, N, L, p, cfg, false);
+}
+
+clusco_status clusco_get_config_batched(clusco_handle h, int64_t N, int64_t L,
+                                        clusco_precision p, clusco_config *cfg)
+{
+    return get_config(h, N, L, p, cfg, true);
 }
 
 clusco_status clusco_force_config(clusco_handle h, const clusco_config *cfg)

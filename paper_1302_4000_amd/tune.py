@@ -7,7 +7,16 @@ is best over that range.  For every precision and every (N bucket, L bucket)
 this script times the whole all-vs-all call (prep, contraction with the
 Eq. 2 epilogue, FP64 fix-up) on a synthetic ensemble of the bucket's
 representative size, for each candidate configuration forced through
-clusco_force_config, and records the fastest:
+clusco_force_config, and records the fastest.  Then the same inside a
+batched call (an entry with "call": "batched"), where the per-call costs are
+shared and the best choice for small ensembles differs: k such ensembles (k
+from BATCH_PAIRS, at most 32) are added to a fixed background of typical
+batch work (BACKGROUNDS: ensembles in the reference frame with three
+products, so the batch already pays for the reference pass and a
+three-product tile launch; never of the bucket being timed) and each
+candidate is set for the bucket through a temporary table; the background's
+share is the same for every candidate, so the fastest batch is the bucket's
+best marginal choice:
 
   products   split-BF16 only: 3 or 4 MFMA products per K-block (4 costs a
              third more MFMA issue and leaves far fewer pairs to the fix-up)
@@ -38,6 +47,11 @@ import numpy as np
 
 # Bucket lower bounds.  N: powers of two from 256 to 16384 (the last bucket
 # holds the paper's largest sets); L: 64 to 512 residues.
+# Pairs of the k ensembles a bucket is timed with for its batched entry, and
+# the background batch they join: (N, L) of each background ensemble (all in
+# one bucket); the bucket of the first background is timed with the second.
+BATCH_PAIRS = 2_000_000
+BACKGROUNDS = [[(1448, 181), (1448, 181)], [(2896, 362)]]
 N_EDGES = [2, 256, 512, 1024, 2048, 4096, 8192, 16384]
 L_EDGES = [1, 64, 128, 256, 512]
 PRECISIONS = {"fp32": "fp32", "split_bf16": "bf16", "split_fp16": "fp16",
@@ -53,6 +67,11 @@ def representative(edges, i, top, floor):
     if hi is None:
         return top
     return int(round(math.sqrt(lo * hi)))
+
+
+def bucket(edges, x):
+    """Index of the bucket of x (edges: ascending lower bounds)."""
+    return max(i for i, e in enumerate(edges) if x >= e)
 
 
 def log(*a):
@@ -111,8 +130,14 @@ def main(argv=None):
     arch = getattr(props, "gcnArchName", "gfx950").split(":")[0]
     out_path = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning",
                                         f"{arch}.json")
+    os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
     binding.load_tuning(None)          # time with no table in the way
     precs = [p for p in args.precisions.split(",") if p]
+    bgs = [([torch.from_numpy(synth.make_ensemble(9000 + 8 * g + m, n, l, sigma=(0.5, 6.0)))
+             for m, (n, l) in enumerate(shapes)],
+            (bucket(N_EDGES, shapes[0][0]), bucket(L_EDGES, shapes[0][1])), shapes)
+           for g, shapes in enumerate(BACKGROUNDS)]
+    tmp_table = out_path + ".candidate.json"
     entries = []
     t_start = time.time()
     for nb in range(len(N_EDGES)):
@@ -123,6 +148,12 @@ def main(argv=None):
                                                      sigma=(0.5, 6.0))).to(dev)
             P = N * (N - 1) // 2
             out = torch.empty(P, dtype=torch.float32, device=dev)
+            k = max(1, min(32, round(BATCH_PAIRS / P)))
+            background, bg_bucket, bg_shapes = bgs[1] if (nb, lb) == bgs[0][1] else bgs[0]
+            batch = binding.Batch(bg_shapes + [(N, L)] * k)
+            flat = batch.pack(background + [x.cpu()] + [torch.from_numpy(synth.make_ensemble(
+                7000 + 16 * nb + lb + 4096 * m, N, L, sigma=(0.5, 6.0))) for m in range(1, k)], dev)
+            bout = torch.empty(batch.n_out, dtype=torch.float32, device=dev)
             for prec in precs:
                 p = PRECISIONS[prec]
                 ws = torch.empty(max(256, binding.workspace_size(N, L, p)), dtype=torch.uint8,
@@ -145,7 +176,40 @@ def main(argv=None):
                 log(f"[tune] {prec:13s} N={N:6d} L={L:4d}: {best:22s} {ms[best]:8.3f} ms "
                     f"(default {ms.get(default, float('nan')):8.3f} ms)")
                 del ws
-            del x, out
+                # the same bucket's k ensembles inside a batched call with the
+                # background, the candidate set for the bucket by a table
+                bws = torch.empty(max(256, binding.batched_workspace_size(batch, p)),
+                                  dtype=torch.uint8, device=dev)
+                bms = {}
+                for prod, sch, band, fr in candidates(prec, N):
+                    ents = [
+                        {"precision": prec, "n_bucket": bg_bucket[0], "l_bucket": bg_bucket[1],
+                         "call": "batched", "products": 4 if prec == "split_bf16x4" else 3,
+                         "schedule": "staged", "band": 16, "frame": 1}]
+                    ents.append({"precision": prec, "n_bucket": nb, "l_bucket": lb,
+                                 "call": "batched", "products": prod, "schedule": sch,
+                                 "band": band, "frame": fr})
+                    with open(tmp_table, "w") as f:
+                        json.dump({"arch": arch, "n_edges": N_EDGES, "l_edges": L_EDGES,
+                                   "entries": ents}, f)
+                    binding.load_tuning(tmp_table)
+                    bms[f"x{prod}/{sch}/{band}/f{fr}"] = time_call(
+                        torch, lambda: binding.crmsd_batched(batch, flat, p, out=bout, ws=bws))
+                binding.load_tuning(None)
+                bbest = min(bms, key=bms.get)
+                if default in bms and bms[default] <= bms[bbest] * (1.0 + args.margin):
+                    bbest = default
+                prod, sch, band, fr = bbest.split("/")
+                entries.append({"precision": prec, "n_bucket": nb, "l_bucket": lb,
+                                "call": "batched", "N": N, "L": L, "ensembles": k,
+                                "background": bg_shapes,
+                                "products": int(prod[1:]), "schedule": sch, "band": int(band),
+                                "frame": int(fr[1:]), "ms": bms,
+                                "batch_pairs_per_s": batch.n_out / (bms[bbest] * 1e-3)})
+                log(f"[tune] {prec:13s} N={N:6d} L={L:4d} batched x{k}: {bbest:22s} "
+                    f"{bms[bbest]:8.3f} ms")
+                del bws
+            del x, out, flat, bout
             torch.cuda.empty_cache()
     table = {
         "arch": arch,
@@ -156,12 +220,17 @@ def main(argv=None):
         "workload": "per bucket: one synthetic ensemble of the representative (N, L), "
                     "sigma ~ U(0.5, 6) A (paper_1302_4000_amd.synth.make_ensemble, seed "
                     "7000 + 16 n_bucket + l_bucket); time of the whole all-vs-all call "
-                    "(median of 5 samples, HIP events)",
+                    "(median of 5 samples, HIP events); batched entries: one batched call "
+                    "over the background (ensembles of the listed shapes, seeds 9000 + 8 g + m, "
+                    "three products in the reference frame) and k = clamp(2e6 / pairs, "
+                    "1, 32) ensembles of the bucket (further seeds + 4096 m) under each "
+                    "candidate",
         "n_edges": N_EDGES,
         "l_edges": L_EDGES,
         "entries": entries,
     }
-    os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
+    if os.path.exists(tmp_table):
+        os.remove(tmp_table)
     with open(out_path, "w") as f:
         json.dump(table, f, indent=1)
     log(f"[tune] wrote {out_path} ({len(entries)} entries, {table['tuning_seconds']} s)")

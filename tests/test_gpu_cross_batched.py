@@ -84,8 +84,15 @@ def test_batched_matches_oracle_and_single_calls(cl, prec):
         got = part.cpu().numpy().astype(np.float64)
         want = oracle.crmsd_matrix(e)
         assert np.abs(got - want).max() < TOL[prec], e.shape
-        single = cl.crmsd_matrix(dev(e), prec).cpu()
-        assert torch.equal(single, part.cpu()), e.shape
+        # the same arithmetic as a single call with the configuration the
+        # batch gives this ensemble (the table's batched entry)
+        c = cl.get_config(e.shape[0], e.shape[1], prec, batched=True)
+        cl.force_config(c["products"], c["schedule"], c["band"], c["frame"])
+        try:
+            single = cl.crmsd_matrix(dev(e), prec).cpu()
+        finally:
+            cl.force_config(None)
+        assert torch.equal(single, part.cpu()), (e.shape, c)
 
 
 def test_batched_graph_replay_is_stable(cl):

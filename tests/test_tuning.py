@@ -37,11 +37,13 @@ def write(tmp_path, obj, name="t.json"):
     return str(p)
 
 
-def entry(prec, nb, lb, products=3, schedule="staged", band=16, frame=None):
+def entry(prec, nb, lb, products=3, schedule="staged", band=16, frame=None, call=None):
     e = {"precision": prec, "n_bucket": nb, "l_bucket": lb, "products": products,
          "schedule": schedule, "band": band, "ms": {"ignored": 1.0}}
     if frame is not None:
         e["frame"] = frame
+    if call is not None:
+        e["call"] = call
     return e
 
 
@@ -91,6 +93,8 @@ def test_lookup_by_bucket(tmp_path):
     json.dumps(table([entry("split_bf16", 0, 0, schedule="looped")])),
     json.dumps(table([entry("split_bf16", 0, 0, band=0)])),
     json.dumps(table([entry("split_bf16", 0, 0, frame=2)])),
+    json.dumps(table([entry("split_bf16", 0, 0, call="sometimes")])),
+    json.dumps(table([entry("split_bf16", 0, 0, call=1)])),
     json.dumps(table([entry("fp64", 0, 0)])),                                    # no tile kernel
     json.dumps(table([], n_edges=(256, 2))),                                     # not ascending
     json.dumps(table([{"precision": "fp32", "n_bucket": 0}])),                   # incomplete
@@ -104,6 +108,49 @@ def test_malformed_table_rejected_and_table_unchanged(tmp_path, bad):
     assert ei.value.status == binding.ERR_INVALID_ARG
     assert binding.get_config(100, 50, "bf16") == before
     assert binding.tuning_path().endswith("good.json")
+
+
+def test_batched_entries(tmp_path):
+    """Batched calls take a bucket's "batched" entry, single calls its
+    single-call entry (in either order in the file); a bucket without a
+    batched entry gives batched calls its single-call entry, and one with
+    only a batched entry gives single calls the built-in default."""
+    t = table([entry("split_bf16", 0, 0, 3, "staged", 16, frame=1, call="batched"),
+               entry("split_bf16", 0, 0, 4, "persistent", 8, frame=0),
+               entry("split_bf16", 1, 0, 4, "staged", 8, frame=0, call="single"),
+               entry("split_bf16", 1, 0, 3, "staged", 32, frame=1, call="batched"),
+               entry("split_bf16", 2, 0, 4, "staged", 24, frame=0),
+               entry("fp32", 0, 0, 3, "staged", 8, frame=1, call="batched")])
+    binding.load_tuning(write(tmp_path, t))
+    single = binding.get_config(100, 50, "bf16")
+    batched = binding.get_config(100, 50, "bf16", batched=True)
+    assert (single["products"], single["schedule"], single["band"], single["frame"]) == \
+        (4, "persistent", 8, 0)
+    assert (batched["products"], batched["schedule"], batched["band"], batched["frame"]) == \
+        (3, "staged", 16, 1)
+    assert single["bucket"] == batched["bucket"] == 0
+    assert batched["source"] == "table"
+    c = binding.get_config(300, 50, "bf16")
+    assert (c["products"], c["band"], c["frame"]) == (4, 8, 0)
+    c = binding.get_config(300, 50, "bf16", batched=True)
+    assert (c["products"], c["band"], c["frame"]) == (3, 32, 1)
+    # no batched entry: the single-call entry
+    assert binding.get_config(5000, 50, "bf16", batched=True) == binding.get_config(5000, 50, "bf16")
+    assert binding.get_config(5000, 50, "bf16")["band"] == 24
+    # only a batched entry: single calls get the default
+    assert binding.get_config(100, 50, "fp32") == DEFAULT
+    assert binding.get_config(100, 50, "fp32", batched=True)["band"] == 8
+    # no table: the default for both
+    binding.load_tuning(None)
+    assert binding.get_config(100, 50, "bf16", batched=True) == DEFAULT
+    # forcing applies to both
+    binding.load_tuning(write(tmp_path, t))
+    binding.force_config(4, "staged", 12, frame=0)
+    try:
+        assert binding.get_config(100, 50, "bf16", batched=True)["band"] == 12
+        assert binding.get_config(100, 50, "bf16")["band"] == 12
+    finally:
+        binding.force_config(None)
 
 
 def test_missing_file_rejected(tmp_path):
@@ -136,11 +183,14 @@ def test_committed_table_covers_every_bucket():
     assert t["arch"] == "gfx950"
     binding.load_tuning(COMMITTED)
     nN, nL = len(t["n_edges"]), len(t["l_edges"])
-    seen = {(e["precision"], e["n_bucket"], e["l_bucket"]) for e in t["entries"]}
-    for prec in ("fp32", "split_bf16", "split_fp16", "split_bf16x4"):
-        for i in range(nN):
-            for j in range(nL):
-                assert (prec, i, j) in seen, (prec, i, j)
+    seen = {(e["precision"], e["n_bucket"], e["l_bucket"], e.get("call", "single"))
+            for e in t["entries"]}
+    calls = {e.get("call", "single") for e in t["entries"]}
+    for call in calls:
+        for prec in ("fp32", "split_bf16", "split_fp16", "split_bf16x4"):
+            for i in range(nN):
+                for j in range(nL):
+                    assert (prec, i, j, call) in seen, (prec, i, j, call)
     # each entry's choice is its fastest measured candidate (within the margin
     # that keeps the default) and what the library reports for the bucket
     name = {"fp32": "fp32", "split_bf16": "bf16", "split_fp16": "fp16", "split_bf16x4": "bf16x4"}
@@ -150,7 +200,8 @@ def test_committed_table_covers_every_bucket():
             key += f"/f{e['frame']}"
         assert key in e["ms"]
         assert e["ms"][key] <= min(e["ms"].values()) * 1.0201
-        c = binding.get_config(e["N"], e["L"], name[e["precision"]])
+        c = binding.get_config(e["N"], e["L"], name[e["precision"]],
+                               batched=e.get("call") == "batched")
         frame = e.get("frame", 1) if e["schedule"] == "staged" else 0
         assert (c["products"], c["schedule"], c["band"], c["frame"], c["source"]) == \
             (e["products"], e["schedule"], e["band"], frame, "table")
