@@ -37,10 +37,12 @@ stream).  The table is loaded by the library at handle creation
 from __future__ import annotations
 
 import argparse
+import atexit
 import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -137,7 +139,9 @@ def main(argv=None):
              for m, (n, l) in enumerate(shapes)],
             (bucket(N_EDGES, shapes[0][0]), bucket(L_EDGES, shapes[0][1])), shapes)
            for g, shapes in enumerate(BACKGROUNDS)]
-    tmp_table = out_path + ".candidate.json"
+    tmp_fd, tmp_table = tempfile.mkstemp(suffix=".json", prefix="clusco_candidate_")
+    os.close(tmp_fd)
+    atexit.register(lambda: os.path.exists(tmp_table) and os.remove(tmp_table))
     entries = []
     t_start = time.time()
     for nb in range(len(N_EDGES)):
@@ -229,8 +233,6 @@ def main(argv=None):
         "l_edges": L_EDGES,
         "entries": entries,
     }
-    if os.path.exists(tmp_table):
-        os.remove(tmp_table)
     with open(out_path, "w") as f:
         json.dump(table, f, indent=1)
     log(f"[tune] wrote {out_path} ({len(entries)} entries, {table['tuning_seconds']} s)")
