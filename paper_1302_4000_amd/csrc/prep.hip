@@ -17,6 +17,8 @@
 namespace clusco {
 
 constexpr int PREP_W = 8;
+// atoms per lane whose loads a round of the atom loops issues together
+constexpr int PREP_U = 4;
 static_assert(REF_CANDIDATES <= PREP_W, "a group holds every reference candidate");
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -155,12 +157,22 @@ __global__ __launch_bounds__(256) void ref_moments_kernel(PrepLaunch a)
 // group returns the choice.
 __device__ __forceinline__ int ref_choice(const double *info, int K, int sl, int base)
 {
+    // Pair (p, q), p < q, is entry p (2 REF_CANDIDATES - p - 1) / 2 + q - p - 1.
+    // The row's entries are loaded without branches (all lie in the info
+    // block; those past K are not used) and summed in ascending order of the
+    // partner, which is ascending entry order.
+    const int me = sl < REF_CANDIDATES ? sl : 0;
+    double v[REF_CANDIDATES];
+#pragma unroll
+    for (int k = 0; k < REF_CANDIDATES; ++k) {
+        const int p = k < me ? k : me, q = k < me ? me : k;
+        v[k] = k == me ? 0.0 : info[p * (2 * REF_CANDIDATES - p - 1) / 2 + q - p - 1];
+    }
     double sum = 0.0;
     if (sl < K) {
-        int t = 0;
-        for (int p = 0; p < REF_CANDIDATES; ++p)
-            for (int q = p + 1; q < REF_CANDIDATES; ++q, ++t)
-                if (q < K && (p == sl || q == sl)) sum += info[t];
+#pragma unroll
+        for (int k = 0; k < REF_CANDIDATES; ++k)
+            if (k != me && k < K) sum += v[k];
     }
     int best = 0;
     double bsum = __shfl(sum, base, 64);
@@ -220,25 +232,44 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 
     // pass 1: the centroid and, in the frame, sum x r^T with r the centred
     // reference (= sum (x - c) r^T, since sum r = 0)
+    // Both passes take the lane's atoms PREP_U at a time: the loads of a
+    // round are issued together, without branches, before any is used (one
+    // memory latency per round instead of one or two per atom).  Atoms past
+    // L load atom L - 1 (always there; xr is x itself without the frame) and
+    // add exact zeros, so the sums are those of one atom at a time in order.
     double m1[12];
 #pragma unroll
     for (int t = 0; t < 12; ++t) m1[t] = 0.0;
     if (real) {
-        for (int64_t l = sl; l < L; l += PREP_W) {
-            double xv[3];
+        for (int64_t l0 = sl; l0 < L; l0 += PREP_U * PREP_W) {
+            float xs[PREP_U][3], rs[PREP_U][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                xv[c] = (double)x[3 * l + c];
-                m1[c] += xv[c];
+            for (int u = 0; u < PREP_U; ++u) {
+                const int64_t l = l0 + u * PREP_W, lc = l < L ? l : L - 1;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[u][c] = x[3 * lc + c];
+                    rs[u][c] = xr[3 * lc + c];
+                }
             }
-            if (frame) {
-                double rv[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) rv[c] = (double)xr[3 * l + c] - cr[c];
+            for (int u = 0; u < PREP_U; ++u) {
+                const bool in = l0 + u * PREP_W < L;
+                double xv[3];
 #pragma unroll
-                for (int p = 0; p < 3; ++p)
+                for (int c = 0; c < 3; ++c) {
+                    xv[c] = in ? (double)xs[u][c] : 0.0;
+                    m1[c] += xv[c];
+                }
+                if (frame) {
+                    double rv[3];
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) m1[3 + 3 * p + q] = fma(xv[p], rv[q], m1[3 + 3 * p + q]);
+                    for (int c = 0; c < 3; ++c) rv[c] = in ? (double)rs[u][c] - cr[c] : 0.0;
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) m1[3 + 3 * p + q] = fma(xv[p], rv[q], m1[3 + 3 * p + q]);
+                }
             }
         }
     }
@@ -292,65 +323,80 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 #pragma unroll
     for (int t = 0; t < 12; ++t) m2[t] = 0.0;
     const int64_t Lend = MODE == MODE_FP64 ? L : s.Lp;
-    for (int64_t l = sl; l < Lend; l += PREP_W) {
-        const bool in = real && l < L;
-        double av[3], rv[3], dv[3], qv[3];
+    for (int64_t l0 = sl; l0 < Lend; l0 += PREP_U * PREP_W) {
+        float xs[PREP_U][3], rs[PREP_U][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            av[c] = in ? (double)x[3 * l + c] - cc[c] : 0.0;
-            rv[c] = (in && frame) ? (double)xr[3 * l + c] - cr[c] : 0.0;
-            m2[0] = fma(av[c], av[c], m2[0]);
-        }
-        if (MODE == MODE_FP64) continue;
+        for (int u = 0; u < PREP_U; ++u) {
+            const int64_t l = l0 + u * PREP_W, lc = l < L ? l : L - 1;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            dv[c] = frame ? fma(rot[3 * c], av[0], fma(rot[3 * c + 1], av[1], fma(rot[3 * c + 2], av[2], -rv[c])))
-                          : av[c];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double v = dv[c];
-            if (MODE == MODE_FP32) {
-                const float f = (float)v;
-                qv[c] = (double)f;
-                const int64_t kb = l >> 3, h = (l >> 2) & 1, el = l & 3;
-                const int64_t idx = (((R * KB + kb) * 3 + c) * 64 + r + 32 * h) * 4 + el;
-                if (live) ((float *)(a.ws + s.ops))[idx] = f;
-            } else {
-                const int64_t kb = l >> 4, h = (l >> 3) & 1, el = l & 7;
-                const int64_t base = (((R * KB + kb) * 3 + c) * 2) * 64;
-                const int64_t hi_idx = (base + r + 32 * h) * 8 + el;
-                const int64_t lo_idx = (base + 64 + r + 32 * h) * 8 + el;
-                uint16_t *ops = (uint16_t *)(a.ws + s.ops);
-                double hv, lv;
-                if (is_bf16(MODE)) {
-                    const uint16_t hb = bf16_bits_rn((float)v);
-                    hv = (double)bf16_bits_to_float(hb);
-                    const uint16_t lb = bf16_bits_rn((float)(v - hv));
-                    lv = (double)bf16_bits_to_float(lb);
-                    if (live) {
-                        ops[hi_idx] = hb;
-                        ops[lo_idx] = lb;
-                    }
-                } else {
-                    const _Float16 hh = (_Float16)(float)v;
-                    hv = (double)(float)hh;
-                    const _Float16 ll = (_Float16)(float)(v - hv);
-                    lv = (double)(float)ll;
-                    if (live) {
-                        ops[hi_idx] = __builtin_bit_cast(uint16_t, hh);
-                        ops[lo_idx] = __builtin_bit_cast(uint16_t, ll);
-                    }
-                }
-                qv[c] = hv + lv;   // exact in FP64
+            for (int c = 0; c < 3; ++c) {
+                xs[u][c] = x[3 * lc + c];
+                rs[u][c] = xr[3 * lc + c];
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            m2[2] = fma(qv[c], qv[c], m2[2]);
-            const double sv = rv[c] + qv[c];
-            m2[1] = fma(sv, sv, m2[1]);
+        for (int u = 0; u < PREP_U; ++u) {
+            const int64_t l = l0 + u * PREP_W;
+            if (l >= Lend) break;
+            const bool in = real && l < L;
+            double av[3], rv[3], dv[3], qv[3];
 #pragma unroll
-            for (int t = 0; t < 3; ++t) m2[3 + 3 * c + t] = fma(qv[c], rv[t], m2[3 + 3 * c + t]);
+            for (int c = 0; c < 3; ++c) {
+                av[c] = in ? (double)xs[u][c] - cc[c] : 0.0;
+                rv[c] = (in && frame) ? (double)rs[u][c] - cr[c] : 0.0;
+                m2[0] = fma(av[c], av[c], m2[0]);
+            }
+            if (MODE == MODE_FP64) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                dv[c] = frame ? fma(rot[3 * c], av[0], fma(rot[3 * c + 1], av[1], fma(rot[3 * c + 2], av[2], -rv[c])))
+                              : av[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double v = dv[c];
+                if (MODE == MODE_FP32) {
+                    const float f = (float)v;
+                    qv[c] = (double)f;
+                    const int64_t kb = l >> 3, h = (l >> 2) & 1, el = l & 3;
+                    const int64_t idx = (((R * KB + kb) * 3 + c) * 64 + r + 32 * h) * 4 + el;
+                    if (live) ((float *)(a.ws + s.ops))[idx] = f;
+                } else {
+                    const int64_t kb = l >> 4, h = (l >> 3) & 1, el = l & 7;
+                    const int64_t base = (((R * KB + kb) * 3 + c) * 2) * 64;
+                    const int64_t hi_idx = (base + r + 32 * h) * 8 + el;
+                    const int64_t lo_idx = (base + 64 + r + 32 * h) * 8 + el;
+                    uint16_t *ops = (uint16_t *)(a.ws + s.ops);
+                    double hv, lv;
+                    if (is_bf16(MODE)) {
+                        const uint16_t hb = bf16_bits_rn((float)v);
+                        hv = (double)bf16_bits_to_float(hb);
+                        const uint16_t lb = bf16_bits_rn((float)(v - hv));
+                        lv = (double)bf16_bits_to_float(lb);
+                        if (live) {
+                            ops[hi_idx] = hb;
+                            ops[lo_idx] = lb;
+                        }
+                    } else {
+                        const _Float16 hh = (_Float16)(float)v;
+                        hv = (double)(float)hh;
+                        const _Float16 ll = (_Float16)(float)(v - hv);
+                        lv = (double)(float)ll;
+                        if (live) {
+                            ops[hi_idx] = __builtin_bit_cast(uint16_t, hh);
+                            ops[lo_idx] = __builtin_bit_cast(uint16_t, ll);
+                        }
+                    }
+                    qv[c] = hv + lv;   // exact in FP64
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                m2[2] = fma(qv[c], qv[c], m2[2]);
+                const double sv = rv[c] + qv[c];
+                m2[1] = fma(sv, sv, m2[1]);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) m2[3 + 3 * c + t] = fma(qv[c], rv[t], m2[3 + 3 * c + t]);
+            }
         }
     }
     wave_sums<PREP_W>(m2);
