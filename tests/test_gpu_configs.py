@@ -2,7 +2,9 @@
 (products 3 / 4 for split-BF16, staged / persistent schedule, band widths,
 reference frame on / off) against the FP64 oracle, for single ensembles, cross comparisons and
 batches; a batch whose ensembles take different configurations (mixed
-product counts) must equal single calls made under the same table."""
+product counts) must equal single calls made under the same table, and a
+table's batched entries, where it has them, decide the batch's
+configuration."""
 import json
 
 import numpy as np
@@ -146,5 +148,53 @@ def test_mixed_table_batch(cl, tmp_path):
         assert kinds == {3, 4}
         assert {(c["schedule"], c["frame"]) for c in cfgs} == {("staged", 1), ("persistent", 0)}
         check_batch_against_single(cl, ens, "bf16")
+    finally:
+        cl.load_tuning(saved or None)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_batched_table_entries(cl, tmp_path, prec):
+    """A table whose batched entries differ from its single-call entries
+    (single calls: four products without the reference frame; ensembles in
+    a batched call: three products with it): the batch follows the batched
+    entries — each ensemble equals a single call forced to its batched
+    configuration, and at least one differs from its single call under the
+    table (so the batched entries took effect) — and matches the oracle."""
+    name = {"bf16": "split_bf16", "fp32": "fp32"}[prec]
+    entries = []
+    for nb in range(3):
+        for lb in range(3):
+            entries.append({"precision": name, "n_bucket": nb, "l_bucket": lb, "products": 4,
+                            "schedule": "staged", "band": 8, "frame": 0})
+            entries.append({"precision": name, "n_bucket": nb, "l_bucket": lb, "products": 3,
+                            "schedule": "staged", "band": 16, "frame": 1, "call": "batched"})
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    p = tmp_path / "batched.json"
+    p.write_text(json.dumps({"arch": arch, "n_edges": [2, 64, 160], "l_edges": [1, 60, 200],
+                             "entries": entries}))
+    saved = cl.binding.tuning_path()
+    cl.load_tuning(str(p))
+    try:
+        ens = [e for e in batch() if e.shape[0] > 1]
+        say(f"[config] batched-entry table, batch of {len(ens)} {prec}")
+        b = cl.Batch([e.shape[:2] for e in ens])
+        flat = b.pack([torch.from_numpy(e) for e in ens], "cuda")
+        out = cl.crmsd_batched(b, flat, prec)
+        torch.cuda.synchronize()
+        differs = 0
+        for e, part in zip(ens, b.split(out)):
+            cb = cl.get_config(e.shape[0], e.shape[1], prec, batched=True)
+            cs = cl.get_config(e.shape[0], e.shape[1], prec)
+            assert (cb["band"], cb["frame"]) == (16, 1) and (cs["band"], cs["frame"]) == (8, 0)
+            got = part.cpu()
+            assert np.abs(got.numpy().astype(np.float64) - oracle.crmsd_matrix(e)).max() < TOL[prec]
+            cl.force_config(cb["products"], cb["schedule"], cb["band"], cb["frame"])
+            try:
+                forced = cl.crmsd_matrix(dev(e), prec).cpu()
+            finally:
+                cl.force_config(None)
+            assert torch.equal(forced, got), e.shape
+            differs += not torch.equal(cl.crmsd_matrix(dev(e), prec).cpu(), got)
+        assert differs > 0
     finally:
         cl.load_tuning(saved or None)
