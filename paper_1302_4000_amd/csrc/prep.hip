@@ -233,10 +233,11 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
     // pass 1: the centroid and, in the frame, sum x r^T with r the centred
     // reference (= sum (x - c) r^T, since sum r = 0)
     // Both passes take the lane's atoms PREP_U at a time: the loads of a
-    // round are issued together, without branches, before any is used (one
-    // memory latency per round instead of one or two per atom).  Atoms past
-    // L load atom L - 1 (always there; xr is x itself without the frame) and
-    // add exact zeros, so the sums are those of one atom at a time in order.
+    // round are issued together, without per-atom branches, before any is
+    // used (one memory latency per round instead of one or two per atom).
+    // Atoms past L of a real model load atom L - 1 (always there; xr is x
+    // itself without the frame) and add exact zeros, so the sums are those of
+    // one atom at a time in order.
     double m1[12];
 #pragma unroll
     for (int t = 0; t < 12; ++t) m1[t] = 0.0;
@@ -324,14 +325,18 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
     for (int t = 0; t < 12; ++t) m2[t] = 0.0;
     const int64_t Lend = MODE == MODE_FP64 ? L : s.Lp;
     for (int64_t l0 = sl; l0 < Lend; l0 += PREP_U * PREP_W) {
-        float xs[PREP_U][3], rs[PREP_U][3];
+        // padding models (m >= N) load nothing: an empty ensemble has no
+        // coordinates at all
+        float xs[PREP_U][3] = {}, rs[PREP_U][3] = {};
+        if (real) {
 #pragma unroll
-        for (int u = 0; u < PREP_U; ++u) {
-            const int64_t l = l0 + u * PREP_W, lc = l < L ? l : L - 1;
+            for (int u = 0; u < PREP_U; ++u) {
+                const int64_t l = l0 + u * PREP_W, lc = l < L ? l : L - 1;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                xs[u][c] = x[3 * lc + c];
-                rs[u][c] = xr[3 * lc + c];
+                for (int c = 0; c < 3; ++c) {
+                    xs[u][c] = x[3 * lc + c];
+                    rs[u][c] = xr[3 * lc + c];
+                }
             }
         }
 #pragma unroll
