@@ -366,6 +366,23 @@ def backward_leg(cl, torch, steps):
     return res
 
 
+def sizes_leg(cl, torch, steps):
+    """The headline recipe (split-BF16, L = 150) at the smallest and the
+    largest decoy-set size of the paper's I-TASSER benchmark (12,500 and
+    32,000 models per target; Results and Discussion, Table 1): pairs/s of
+    the whole call at each size, with the configuration the table gives it."""
+    from paper_1302_4000_amd import synth
+    res = {}
+    for N in (12500, 32000):
+        x = torch.from_numpy(synth.workload("n20000_l150", N=N)).cuda()
+        r, out = time_path(cl, torch, x, "bf16", steps, 2)
+        r["kernel_config"] = cl.get_config(N, x.shape[1], "bf16")
+        res[f"n{N}_l150"] = r
+        del x, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def threshold_leg(cl, torch, x, steps):
     """Pairs below 3.2 A (the paper's threshold example) on the same
     ensemble, emitted without storing the packed matrix."""
@@ -620,6 +637,9 @@ def main():
         extra["n5000_l300"] = config2_leg(cl, torch, max(3, args.steps // 2), threads,
                                           not args.no_error)
         log(f"[bench] n5000_l300: {extra['n5000_l300']}")
+        log("[bench] decoy-set sizes 12,500 and 32,000 (split-BF16, L=150)")
+        extra["sizes"] = sizes_leg(cl, torch, max(3, args.steps // 2))
+        log(f"[bench] sizes: {extra['sizes']}")
         log("[bench] threshold 3.2 A")
         extra["threshold"] = threshold_leg(cl, torch, x, max(3, args.steps // 2))
         log(f"[bench] threshold: {extra['threshold']}")
