@@ -20,6 +20,10 @@ constexpr int PREP_W = 8;
 // atoms per lane whose loads a round of the atom loops issues together
 constexpr int PREP_U = 4;
 static_assert(REF_CANDIDATES <= PREP_W, "a group holds every reference candidate");
+// The operand stores of pass 2 use that a round of a lane covers atoms
+// sl + 8 i: the element within an 8-atom run is the lane's own, and every
+// store of a round lies at a fixed offset from one base (see pass 2).
+static_assert(PREP_W == 8 && PREP_U % 2 == 0, "pass 2 store addressing");
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -213,12 +217,11 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
     const bool frame = MODE != MODE_FP64 && s.frame != 0;
     const double inv = 1.0 / (double)L;
 
-    // the reference (frame): the chosen candidate's coordinates, centroid
-    // and G from ref_moments_kernel
+    // the reference (frame): the chosen candidate's coordinates and
+    // centroid from ref_moments_kernel (its G is read at the end)
     const float *xr = x;
-    double cr[3] = {0.0, 0.0, 0.0}, G[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) G[t] = 0.0;
+    double cr[3] = {0.0, 0.0, 0.0};
+    int kref = 0;
     if (frame) {
         const double *info = (const double *)(a.ws + s.refinfo);
         const int K = (int)(s.ref_N < REF_CANDIDATES ? s.ref_N : REF_CANDIDATES);
@@ -226,8 +229,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
         xr = (s.ref_b ? a.XB : a.XA) + s.ref_X + (int64_t)k * L * 3;
 #pragma unroll
         for (int t = 0; t < 3; ++t) cr[t] = info[RI_CEN + 3 * k + t];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) G[t] = info[RI_G + 9 * k + t];
+        kref = k;
     }
 
     // pass 1: the centroid and, in the frame, sum x r^T with r the centred
@@ -324,7 +326,17 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
 #pragma unroll
     for (int t = 0; t < 12; ++t) m2[t] = 0.0;
     const int64_t Lend = MODE == MODE_FP64 ? L : s.Lp;
+    // Store addressing from the layout in internal.h with l = l0 + 8 u and
+    // l0 = sl + 8 PREP_U j.  FP32 (K-block 8, runs of 4): kb = PREP_U j + u,
+    // h = sl / 4, e = sl % 4, so (u, c) is at base + 768 u + 256 c floats.
+    // 16-bit (K-block 16, runs of 8): kb = PREP_U j / 2 + u / 2, h = u % 2,
+    // e = sl, so (u, c, part) is at base + 3072 (u / 2) + 256 (u % 2) +
+    // 1024 c + 512 part halves.
+    float *const ops32 = (float *)(a.ws + s.ops) + (R * KB * 3 * 64 + r + 32 * (sl >> 2)) * 4 + (sl & 3);
+    uint16_t *const ops16 = (uint16_t *)(a.ws + s.ops) + (R * KB * 6 * 64 + r) * 8 + sl;
     for (int64_t l0 = sl; l0 < Lend; l0 += PREP_U * PREP_W) {
+        float *const row32 = ops32 + (l0 - sl) / PREP_W * 768;
+        uint16_t *const row16 = ops16 + (l0 - sl) / (2 * PREP_W) * 3072;
         // padding models (m >= N) load nothing: an empty ensemble has no
         // coordinates at all
         float xs[PREP_U][3] = {}, rs[PREP_U][3] = {};
@@ -362,15 +374,9 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
                 if (MODE == MODE_FP32) {
                     const float f = (float)v;
                     qv[c] = (double)f;
-                    const int64_t kb = l >> 3, h = (l >> 2) & 1, el = l & 3;
-                    const int64_t idx = (((R * KB + kb) * 3 + c) * 64 + r + 32 * h) * 4 + el;
-                    if (live) ((float *)(a.ws + s.ops))[idx] = f;
+                    if (live) row32[768 * u + 256 * c] = f;
                 } else {
-                    const int64_t kb = l >> 4, h = (l >> 3) & 1, el = l & 7;
-                    const int64_t base = (((R * KB + kb) * 3 + c) * 2) * 64;
-                    const int64_t hi_idx = (base + r + 32 * h) * 8 + el;
-                    const int64_t lo_idx = (base + 64 + r + 32 * h) * 8 + el;
-                    uint16_t *ops = (uint16_t *)(a.ws + s.ops);
+                    uint16_t *const hi = row16 + 3072 * (u >> 1) + 256 * (u & 1) + 1024 * c;
                     double hv, lv;
                     if (is_bf16(MODE)) {
                         const uint16_t hb = bf16_bits_rn((float)v);
@@ -378,8 +384,8 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
                         const uint16_t lb = bf16_bits_rn((float)(v - hv));
                         lv = (double)bf16_bits_to_float(lb);
                         if (live) {
-                            ops[hi_idx] = hb;
-                            ops[lo_idx] = lb;
+                            hi[0] = hb;
+                            hi[512] = lb;
                         }
                     } else {
                         const _Float16 hh = (_Float16)(float)v;
@@ -387,8 +393,8 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
                         const _Float16 ll = (_Float16)(float)(v - hv);
                         lv = (double)(float)ll;
                         if (live) {
-                            ops[hi_idx] = __builtin_bit_cast(uint16_t, hh);
-                            ops[lo_idx] = __builtin_bit_cast(uint16_t, ll);
+                            hi[0] = __builtin_bit_cast(uint16_t, hh);
+                            hi[512] = __builtin_bit_cast(uint16_t, ll);
                         }
                     }
                     qv[c] = hv + lv;   // exact in FP64
@@ -415,6 +421,7 @@ __global__ __launch_bounds__(64) void prep_kernel(PrepLaunch a)
         ((double *)(a.ws + s.F))[m] = fma(s.fw, m2[2], s.fe * m2[1]);
         double *U = (double *)(a.ws + s.U) + 9 * m;
         double *PT = (double *)(a.ws + s.PT) + 9 * m;
+        const double *G = (const double *)(a.ws + s.refinfo) + RI_G + 9 * kref;
 #pragma unroll
         for (int p = 0; p < 3; ++p)
 #pragma unroll
