@@ -908,7 +908,7 @@ std::vector<int64_t> batch_key(clusco_handle h, int mode, const BatchInput &b, b
     return k;
 }
 
-// Host-side plan: sets in input order, problems sorted by cost per tile
+// Host-side plan: sets by descending length, problems sorted by cost per tile
 // (padded length, then size) so the persistent kernel starts the longest
 // tiles first.  Returns the workspace size; fills tables when asked.
 struct PlanKernel {
@@ -942,9 +942,16 @@ size_t plan_layout(clusco_handle h, int mode, const BatchInput &b, std::vector<M
     }
     const int sched = !framed && vote[SCHED_PERSISTENT] > vote[SCHED_STAGED] ? SCHED_PERSISTENT
                                                                              : SCHED_STAGED;
+    // sets (and so the prep's waves, which take the models in set order) go
+    // longest model first: the longest models' chain of dependent loads sets
+    // the prep's time, so they start before the short ones fill the GPU
+    std::vector<int32_t> order;
+    for (int32_t e = 0; e < b.E; ++e)
+        if (b.N[e] >= 2) order.push_back(e);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return b.L[x] > b.L[y]; });
     int nx4 = 0;
-    for (int32_t e = 0; e < b.E; ++e) {
-        if (b.N[e] < 2) continue;
+    for (const int32_t e : order) {
         ModelSet s = make_set(mode, b.coff ? b.coff[e] : 0, b.N[e], b.L[e], model0, 0, o);
         model0 += s.Np;
         const KernelCfg c = cfg[e];
