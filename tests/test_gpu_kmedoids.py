@@ -40,11 +40,15 @@ def say(*a):
 def compare(cl, D_np, N, k, init, max_iter=100):
     D = torch.from_numpy(np.ascontiguousarray(D_np, dtype=np.float32)).cuda()
     got = cl.kmedoids(D, N, k, init, max_iter)
-    # fully asynchronous mode (every step enqueued) must give the same result
+    # fully asynchronous mode (every step enqueued) and a poll after every
+    # step must give the same result
     other = cl.kmedoids(D, N, k, init, max_iter, check_every=0)
+    each = cl.kmedoids(D, N, k, init, max_iter, check_every=1)
     torch.cuda.synchronize()
     got = {n: t.cpu().numpy() for n, t in got.items()}
     for n, t in other.items():
+        assert np.array_equal(t.cpu().numpy(), got[n]), n
+    for n, t in each.items():
         assert np.array_equal(t.cpu().numpy(), got[n]), n
     want = oracle.kmedoids(D_np, N, k, init, max_iter)
     if want["tie_margin"] > Q * (1 + 1e-6) + 1e-12:
@@ -86,6 +90,11 @@ def test_crmsd_matrix_clusters(cl, N, L, k, seed):
     init = np.random.default_rng(seed).choice(N, k, replace=False)
     r = compare(cl, D, N, k, init)
     say(f"  iterations {r['iterations']} converged {r['converged']} rep {r['rep_cluster']}")
+    # out of steps before convergence (one update that moved a medoid): the
+    # assignment after the last update
+    if r["iterations"] >= 2:
+        r2 = compare(cl, D, N, k, init, max_iter=1)
+        assert not r2["converged"]
 
 
 def test_n5000_against_oracle(cl):
